@@ -1,0 +1,11 @@
+"""Serial FP64 oracle of the repartitioning path (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product library never uses it, and it shares no
+code with the GPU path.
+"""
+from .oracle import (OracleError, Merged, build, loaded_library, merge, receive_buffer,
+                     update, spmv, pcg, true_relres, value_grad, face_grad)
+
+__all__ = ["OracleError", "Merged", "build", "loaded_library", "merge", "receive_buffer",
+           "update", "spmv", "pcg", "true_relres", "value_grad", "face_grad"]

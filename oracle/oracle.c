@@ -1,0 +1,378 @@
+/*
+ * Serial FP64 oracle for the matrix-repartitioning path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * CPU definition of what the GPU library computes.  Only the test suite, the
+ * smoke check and the benchmark's CPU-baseline leg load it; the product
+ * library neither links nor calls it, and the two share no code.
+ *
+ * Built with gcc -O2 -ffp-contract=off (no fused multiply-add, no fast-math):
+ * every product and sum below is one correctly rounded IEEE operation, taken
+ * in the order written.
+ *
+ * Paper: Olenik, Koch, Anzt, "Investigating Matrix Repartitioning to Address
+ * the Over- and Undersubscription Challenge for a GPU-based CFD Solver".
+ *
+ * Readings of the paper used here (the paper leaves these open):
+ *  - LDU layout (Sec. 3 names the LDU host format without defining it):
+ *    A(owner_f, neighbour_f) = upper[f], A(neighbour_f, owner_f) = lower[f],
+ *    A(c, c) = diag[c]; interface value = the matrix entry A(row, col).
+ *  - Global row ids of CPU rank r (the index sets I_CPU(r) of Sec. 3) are the
+ *    contiguous range [off_r, off_r + n_cells_r), off_r = sum of n_cells over
+ *    ranks below r; the GPU part k then owns one contiguous range.
+ *  - Receive-buffer order (Sec. 3, update procedure): ranks of the share in
+ *    order; inside a rank [diag | upper | lower | interface], each in the
+ *    rank's own LDU order.
+ *  - Device order (Sec. 3, "row-major"): rows ascending, columns ascending
+ *    within a row; the local block first, then the non-local block.
+ *  - Preconditioner: Jacobi, M = diag(A) (the paper only names CG, Sec. 4).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_NOT_CONVERGED 1
+#define OR_ERR_ARG (-1)
+#define OR_ERR_MESH (-2)
+#define OR_ERR_OVERFLOW (-3)
+#define OR_ERR_BREAKDOWN (-6)
+
+/* ------------------------------------------------------------------------ *
+ * Sizes of the merged system for the share [first, first + alpha).
+ * ------------------------------------------------------------------------ */
+int or_merge_sizes(int alpha, const int32_t* n_cells_share, const int32_t* n_faces,
+                   const int32_t* n_iface, int64_t* n_rows, int64_t* n_slots)
+{
+    int64_t rows = 0, slots = 0;
+    for (int s = 0; s < alpha; ++s) {
+        rows += n_cells_share[s];
+        slots += (int64_t)n_cells_share[s] + 2 * (int64_t)n_faces[s] + n_iface[s];
+    }
+    *n_rows = rows;
+    *n_slots = slots;
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ *
+ * Repartition (Sec. 3, steps 1-3 and the three resulting structures).
+ *
+ * GPU part k fuses the patterns of CPU ranks first..first+alpha-1 (the
+ * blockwise map of Sec. 3).  Every LDU coefficient of those ranks is one
+ * "slot" of the contiguous receive buffer; the slot's matrix position is
+ *   diag  c   -> (off_r + c,      off_r + c)
+ *   upper f   -> (off_r + own_f,  off_r + nbr_f)
+ *   lower f   -> (off_r + nbr_f,  off_r + own_f)
+ *   iface e   -> (off_r + cell_e, off_q + ncell_e),  q = nbr rank of e
+ * A slot is local when its global column lies in the fused row set
+ * I_GPU = union of I_CPU(r) over the share (the localisation rule of Sec. 3),
+ * non-local otherwise.  Rows are numbered from the start of the share.
+ *
+ * Outputs (caller allocated):
+ *   row_ptr[n_rows+1], col[n_slots] (local column ids; first nnz_local used)
+ *   nl_row_ptr[n_rows+1], nl_col[n_slots] (global column ids)
+ *   perm[n_slots]: slot -> device position (local block 0..nnz_local-1, then
+ *                  the non-local block nnz_local + position); the permutation
+ *                  P of Sec. 3
+ *   slot_off[alpha+1]: receive-buffer offset of each rank's slot block; with
+ *                  the lengths this is the update pattern U of Sec. 3
+ *   slot_row[n_slots], slot_col[n_slots]: matrix position of every slot
+ *                  (row from the share start, column global)
+ *   diag_slot[n_rows]: the slot holding each row's diagonal
+ *   counts[2] = {nnz_local, nnz_nonlocal}
+ * ------------------------------------------------------------------------ */
+int or_merge(int n_ranks_total, const int32_t* n_cells_all, int first, int alpha,
+             const int32_t* n_faces, const int32_t* owner, const int32_t* neighbour,
+             const int32_t* n_iface, const int32_t* iface_cell,
+             const int32_t* iface_nbr_rank, const int32_t* iface_nbr_cell,
+             int32_t* row_ptr, int32_t* col, int32_t* nl_row_ptr, int64_t* nl_col,
+             int32_t* perm, int64_t* slot_off, int32_t* slot_row, int64_t* slot_col,
+             int32_t* diag_slot, int64_t* counts)
+{
+    if (n_ranks_total < 1 || alpha < 1 || first < 0 || first + alpha > n_ranks_total)
+        return OR_ERR_ARG;
+
+    int64_t* off = (int64_t*)malloc(sizeof(int64_t) * (n_ranks_total + 1));
+    off[0] = 0;
+    for (int r = 0; r < n_ranks_total; ++r) {
+        if (n_cells_all[r] < 0) { free(off); return OR_ERR_ARG; }
+        off[r + 1] = off[r] + n_cells_all[r];
+    }
+    const int64_t lo = off[first], hi = off[first + alpha];
+    const int64_t n_rows = hi - lo;
+
+    /* slot coordinates, in buffer order */
+    int64_t k = 0, fbase = 0, ebase = 0;
+    for (int s = 0; s < alpha; ++s) {
+        const int r = first + s;
+        const int64_t nc = n_cells_all[r];
+        const int64_t row0 = off[r] - lo;
+        slot_off[s] = k;
+        for (int64_t c = 0; c < nc; ++c) {
+            slot_row[k] = (int32_t)(row0 + c);
+            slot_col[k] = off[r] + c;
+            diag_slot[row0 + c] = (int32_t)k;
+            ++k;
+        }
+        for (int64_t f = 0; f < n_faces[s]; ++f) {
+            int32_t o = owner[fbase + f], b = neighbour[fbase + f];
+            if (o < 0 || o >= nc || b < 0 || b >= nc || o == b) { free(off); return OR_ERR_MESH; }
+            slot_row[k] = (int32_t)(row0 + o);
+            slot_col[k] = off[r] + b;
+            ++k;
+        }
+        for (int64_t f = 0; f < n_faces[s]; ++f) {
+            int32_t o = owner[fbase + f], b = neighbour[fbase + f];
+            slot_row[k] = (int32_t)(row0 + b);
+            slot_col[k] = off[r] + o;
+            ++k;
+        }
+        for (int64_t e = 0; e < n_iface[s]; ++e) {
+            int32_t c = iface_cell[ebase + e], q = iface_nbr_rank[ebase + e], d = iface_nbr_cell[ebase + e];
+            if (c < 0 || c >= nc || q < 0 || q >= n_ranks_total || q == r || d < 0 || d >= n_cells_all[q]) {
+                free(off);
+                return OR_ERR_MESH;
+            }
+            slot_row[k] = (int32_t)(row0 + c);
+            slot_col[k] = off[q] + d;
+            ++k;
+        }
+        fbase += n_faces[s];
+        ebase += n_iface[s];
+    }
+    slot_off[alpha] = k;
+    const int64_t n_slots = k;
+    if (n_slots >= INT32_MAX || n_rows >= INT32_MAX) { free(off); return OR_ERR_OVERFLOW; }
+
+    /* count entries per row, local and non-local separately */
+    memset(row_ptr, 0, sizeof(int32_t) * (n_rows + 1));
+    memset(nl_row_ptr, 0, sizeof(int32_t) * (n_rows + 1));
+    for (int64_t j = 0; j < n_slots; ++j) {
+        int is_local = slot_col[j] >= lo && slot_col[j] < hi;
+        if (is_local) row_ptr[slot_row[j] + 1]++;
+        else nl_row_ptr[slot_row[j] + 1]++;
+    }
+    for (int64_t i = 0; i < n_rows; ++i) {
+        row_ptr[i + 1] += row_ptr[i];
+        nl_row_ptr[i + 1] += nl_row_ptr[i];
+    }
+    const int64_t nnz_local = row_ptr[n_rows], nnz_nl = nl_row_ptr[n_rows];
+
+    /* place each slot into its row, keeping every row sorted by column
+     * (insertion into the row as slots arrive in buffer order) */
+    int32_t* fill = (int32_t*)calloc((size_t)n_rows, sizeof(int32_t));
+    int32_t* nl_fill = (int32_t*)calloc((size_t)n_rows, sizeof(int32_t));
+    int32_t* at_slot = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz_local > 0 ? nnz_local : 1));
+    int32_t* nl_at_slot = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz_nl > 0 ? nnz_nl : 1));
+    int status = OR_OK;
+    for (int64_t j = 0; j < n_slots && status == OR_OK; ++j) {
+        const int64_t i = slot_row[j];
+        const int64_t cg = slot_col[j];
+        const int is_local = cg >= lo && cg < hi;
+        const int32_t* rp = is_local ? row_ptr : nl_row_ptr;
+        int32_t* fl = is_local ? fill : nl_fill;
+        int32_t* at = is_local ? at_slot : nl_at_slot;
+        int64_t base = rp[i];
+        int64_t m = fl[i];
+        /* shift larger columns right, then drop the slot in */
+        while (m > 0 && slot_col[at[base + m - 1]] > cg) {
+            at[base + m] = at[base + m - 1];
+            --m;
+        }
+        if (m > 0 && slot_col[at[base + m - 1]] == cg) status = OR_ERR_MESH; /* duplicate entry */
+        at[base + m] = (int32_t)j;
+        fl[i]++;
+    }
+    if (status == OR_OK) {
+        for (int64_t p = 0; p < nnz_local; ++p) {
+            col[p] = (int32_t)(slot_col[at_slot[p]] - lo);
+            perm[at_slot[p]] = (int32_t)p;
+        }
+        for (int64_t p = 0; p < nnz_nl; ++p) {
+            nl_col[p] = slot_col[nl_at_slot[p]];
+            perm[nl_at_slot[p]] = (int32_t)(nnz_local + p);
+        }
+        /* interface pairing inside the share: the coupling (c, q, d) on rank p
+         * needs its partner (d, p, c) on rank q, i.e. an interface slot of q at
+         * the transposed position */
+        fbase = 0;
+        for (int s = 0; s < alpha && status == OR_OK; ++s) {
+            const int r = first + s;
+            const int64_t e0 = slot_off[s] + n_cells_all[r] + 2 * (int64_t)n_faces[s];
+            for (int64_t j = e0; j < slot_off[s + 1]; ++j) {
+                const int64_t cg = slot_col[j];
+                if (!(cg >= lo && cg < hi)) continue;
+                const int64_t prow = cg - lo;                /* partner's row */
+                const int64_t want = slot_row[j] + lo;       /* partner's column */
+                int found = 0;
+                for (int64_t p = row_ptr[prow]; p < row_ptr[prow + 1]; ++p) {
+                    if (slot_col[at_slot[p]] == want) {
+                        int64_t js = at_slot[p];
+                        /* js must be an interface slot of the partner rank */
+                        int qs = 0;
+                        while (qs < alpha && !(js >= slot_off[qs] && js < slot_off[qs + 1])) ++qs;
+                        int64_t qe0 = slot_off[qs] + n_cells_all[first + qs] + 2 * (int64_t)n_faces[qs];
+                        found = (js >= qe0);
+                        break;
+                    }
+                }
+                if (!found) { status = OR_ERR_MESH; break; }
+            }
+        }
+    }
+    counts[0] = nnz_local;
+    counts[1] = nnz_nl;
+    free(fill); free(nl_fill); free(at_slot); free(nl_at_slot); free(off);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ *
+ * Coefficient update (Sec. 3, update procedure): the receive buffer, ordered
+ * by originating rank and LDU order, is reordered by P into the device value
+ * array.  FP32 copies are round-to-nearest-even casts; the Jacobi inverse is
+ * one correctly rounded FP64 division, then cast.
+ * ------------------------------------------------------------------------ */
+void or_update(int64_t n_rows, int64_t n_slots, const int32_t* perm, const int32_t* diag_slot,
+               const double* buf, double* val64, float* val32, double* dinv64, float* dinv32)
+{
+    for (int64_t k = 0; k < n_slots; ++k) val64[perm[k]] = buf[k];
+    for (int64_t p = 0; p < n_slots; ++p) val32[p] = (float)val64[p];
+    for (int64_t i = 0; i < n_rows; ++i) {
+        dinv64[i] = 1.0 / buf[diag_slot[i]];
+        dinv32[i] = (float)dinv64[i];
+    }
+}
+
+/* y = A x over the local block: each row summed from 0.0 in column order */
+void or_spmv(int64_t n_rows, const int32_t* row_ptr, const int32_t* col, const double* val,
+             const double* x, double* y)
+{
+    for (int64_t i = 0; i < n_rows; ++i) {
+        double s = 0.0;
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) s += val[p] * x[col[p]];
+        y[i] = s;
+    }
+}
+
+static double dot(int64_t n, const double* a, const double* b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* ‖b − A x‖₂ / ‖b‖₂ (0 when b = 0 and x = 0) */
+double or_true_relres(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                      const double* b, const double* x)
+{
+    double* y = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    or_spmv(n, row_ptr, col, val, x, y);
+    double rr = 0.0, bb = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double d = b[i] - y[i];
+        rr += d * d;
+        bb += b[i] * b[i];
+    }
+    free(y);
+    if (bb == 0.0) return sqrt(rr);
+    return sqrt(rr) / sqrt(bb);
+}
+
+/* ------------------------------------------------------------------------ *
+ * Jacobi-preconditioned conjugate gradients (the CG of Sec. 4 with
+ * M = diag(A)), in the textbook order of preconditioned CG:
+ *   r = b − A x, z = M⁻¹ r, p = z
+ *   repeat: q = A p; a = (r,z)/(q,p); x += a p; r −= a q;
+ *           stop if ‖r‖ ≤ tol ‖b‖;
+ *           z = M⁻¹ r; beta = (r,z)_new/(r,z)_old; p = z + beta p
+ * When the recurrence residual passes, the true residual ‖b − A x‖ is checked;
+ * if it fails, CG restarts from the current x (at most max_restarts times).
+ * b = 0 gives x = 0 with no iteration.
+ * out[0] = iterations, out[1] = restarts; res[0] = true rel. residual.
+ * ------------------------------------------------------------------------ */
+int or_pcg(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+           const double* b, double* x, double tol, int64_t max_iter, int max_restarts,
+           int64_t* out, double* res)
+{
+    double* diag = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* r = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* z = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* p = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* q = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int status = OR_NOT_CONVERGED;
+    int64_t it = 0;
+    int restarts = 0;
+
+    for (int64_t i = 0; i < n; ++i) {
+        diag[i] = 0.0;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            if (col[k] == i) diag[i] = val[k];
+    }
+    const double bnorm = sqrt(dot(n, b, b));
+    if (bnorm == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        status = OR_OK;
+        goto done;
+    }
+    for (;;) {
+        or_spmv(n, row_ptr, col, val, x, q);
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+        if (sqrt(dot(n, r, r)) <= tol * bnorm) { status = OR_OK; break; }
+        for (int64_t i = 0; i < n; ++i) z[i] = r[i] / diag[i];
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i];
+        double rz = dot(n, r, z);
+        int passed = 0;
+        while (it < max_iter) {
+            or_spmv(n, row_ptr, col, val, p, q);
+            const double pq = dot(n, p, q);
+            if (!(pq > 0.0) || !isfinite(pq)) { status = OR_ERR_BREAKDOWN; goto done; }
+            const double a = rz / pq;
+            for (int64_t i = 0; i < n; ++i) x[i] += a * p[i];
+            for (int64_t i = 0; i < n; ++i) r[i] -= a * q[i];
+            ++it;
+            if (sqrt(dot(n, r, r)) <= tol * bnorm) { passed = 1; break; }
+            for (int64_t i = 0; i < n; ++i) z[i] = r[i] / diag[i];
+            const double rz_new = dot(n, r, z);
+            const double beta = rz_new / rz;
+            rz = rz_new;
+            for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        }
+        if (!passed) break;                     /* iteration budget spent */
+        if (or_true_relres(n, row_ptr, col, val, b, x) <= tol) { status = OR_OK; break; }
+        if (restarts >= max_restarts) break;
+        ++restarts;
+    }
+done:
+    out[0] = it;
+    out[1] = restarts;
+    res[0] = or_true_relres(n, row_ptr, col, val, b, x);
+    free(diag); free(r); free(z); free(p); free(q);
+    return status;
+}
+
+/* Gradient of L with respect to every receive-buffer slot for A x = b:
+ * dL/dv_k = −lambda_row(k) · x_col(k), lambda = A^-T dL/dx.  Columns are
+ * global ids; only local slots (column inside [lo, lo + n_rows)) are defined,
+ * non-local slots get 0. */
+void or_value_grad(int64_t n_slots, const int32_t* slot_row, const int64_t* slot_col, int64_t lo,
+                   int64_t n_rows, const double* lambda, const double* x, double* g)
+{
+    for (int64_t k = 0; k < n_slots; ++k) {
+        const int64_t c = slot_col[k] - lo;
+        g[k] = (c >= 0 && c < n_rows) ? -lambda[slot_row[k]] * x[c] : 0.0;
+    }
+}
+
+/* Gradient with respect to face coefficients c_f of
+ * A = sum_f c_f (e_a − e_b)(e_a − e_b)^T + sum_walls c_w e_a e_a^T:
+ * interior face: −(lambda_a − lambda_b)(x_a − x_b); wall (b < 0): −lambda_a x_a. */
+void or_face_grad(int64_t n_faces, const int64_t* row_a, const int64_t* row_b,
+                  const double* lambda, const double* x, double* g)
+{
+    for (int64_t f = 0; f < n_faces; ++f) {
+        const int64_t a = row_a[f], b = row_b[f];
+        if (b >= 0) g[f] = -(lambda[a] - lambda[b]) * (x[a] - x[b]);
+        else g[f] = -lambda[a] * x[a];
+    }
+}

@@ -1,0 +1,207 @@
+"""ctypes access to the serial FP64 oracle in oracle.c (test infrastructure only).
+
+Paper sections cited per function; the C source carries the definitions.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "oracle.c")
+LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_I32 = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_I64 = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+_F64 = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_F32 = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"oracle {what} failed with status {code}")
+        self.code = code
+
+
+def build() -> str:
+    """Compile the oracle: plain gcc, no FMA contraction, no fast-math."""
+    tmp = LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                           "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def loaded_library():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        lib = C.CDLL(LIB)
+        lib.or_merge_sizes.argtypes = [C.c_int, _I32, _I32, _I32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        lib.or_merge.argtypes = [C.c_int, _I32, C.c_int, C.c_int, _I32, _I32, _I32, _I32, _I32, _I32, _I32,
+                                 _I32, _I32, _I32, _I64, _I32, _I64, _I32, _I64, _I32, _I64]
+        lib.or_update.argtypes = [C.c_int64, C.c_int64, _I32, _I32, _F64, _F64, _F32, _F64, _F32]
+        lib.or_spmv.argtypes = [C.c_int64, _I32, _I32, _F64, _F64, _F64]
+        lib.or_true_relres.argtypes = [C.c_int64, _I32, _I32, _F64, _F64, _F64]
+        lib.or_true_relres.restype = C.c_double
+        lib.or_pcg.argtypes = [C.c_int64, _I32, _I32, _F64, _F64, _F64, C.c_double, C.c_int64, C.c_int,
+                               _I64, _F64]
+        lib.or_value_grad.argtypes = [C.c_int64, _I32, _I64, C.c_int64, C.c_int64, _F64, _F64, _F64]
+        lib.or_face_grad.argtypes = [C.c_int64, _I64, _I64, _F64, _F64, _F64]
+        _lib = lib
+    return _lib
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _cat(ranks, key):
+    parts = [np.asarray(r[key], dtype=np.int32) for r in ranks]
+    return np.ascontiguousarray(np.concatenate(parts) if parts else np.zeros(0, np.int32), dtype=np.int32)
+
+
+@dataclass
+class Merged:
+    """The three structures of the repartitioning (Sec. 3): pattern, update
+    pattern (slot_off) and permutation P (perm), plus slot coordinates."""
+    first: int
+    alpha: int
+    lo: int                 # global id of the first fused row
+    n_rows: int
+    n_slots: int
+    nnz_local: int
+    nnz_nonlocal: int
+    row_ptr: np.ndarray
+    col: np.ndarray
+    nl_row_ptr: np.ndarray
+    nl_col: np.ndarray
+    perm: np.ndarray
+    slot_off: np.ndarray
+    slot_row: np.ndarray
+    slot_col: np.ndarray
+    diag_slot: np.ndarray
+
+
+def merge(n_cells_all, first: int, alpha: int, ranks: list) -> Merged:
+    """Fuse the LDU patterns of CPU ranks first..first+alpha-1 (Sec. 3, steps
+    1-3, the localisation rule and the three resulting structures).  ranks[s]
+    holds owner/neighbour/iface_cell/iface_nbr_rank/iface_nbr_cell of rank
+    first+s."""
+    lib = loaded_library()
+    n_cells_all = _i32(n_cells_all)
+    if alpha < 1 or first < 0 or first + alpha > len(n_cells_all) or len(ranks) != alpha:
+        raise OracleError(-1, "merge (share outside the rank range)")
+    nc_share = _i32([n_cells_all[first + s] for s in range(alpha)])
+    nf = _i32([len(r["owner"]) for r in ranks])
+    ni = _i32([len(r["iface_cell"]) for r in ranks])
+    n_rows, n_slots = C.c_int64(), C.c_int64()
+    lib.or_merge_sizes(alpha, nc_share, nf, ni, C.byref(n_rows), C.byref(n_slots))
+    nr, ns = n_rows.value, n_slots.value
+    row_ptr = np.zeros(nr + 1, np.int32)
+    col = np.zeros(max(ns, 1), np.int32)
+    nl_row_ptr = np.zeros(nr + 1, np.int32)
+    nl_col = np.zeros(max(ns, 1), np.int64)
+    perm = np.zeros(max(ns, 1), np.int32)
+    slot_off = np.zeros(alpha + 1, np.int64)
+    slot_row = np.zeros(max(ns, 1), np.int32)
+    slot_col = np.zeros(max(ns, 1), np.int64)
+    diag_slot = np.zeros(max(nr, 1), np.int32)
+    counts = np.zeros(2, np.int64)
+    st = lib.or_merge(len(n_cells_all), n_cells_all, first, alpha, nf,
+                      _cat(ranks, "owner"), _cat(ranks, "neighbour"), ni,
+                      _cat(ranks, "iface_cell"), _cat(ranks, "iface_nbr_rank"), _cat(ranks, "iface_nbr_cell"),
+                      row_ptr, col, nl_row_ptr, nl_col, perm, slot_off, slot_row, slot_col, diag_slot, counts)
+    if st != 0:
+        raise OracleError(st, "merge")
+    nnz, nnz_nl = int(counts[0]), int(counts[1])
+    lo = int(np.sum(n_cells_all[:first], dtype=np.int64))
+    return Merged(first, alpha, lo, nr, ns, nnz, nnz_nl, row_ptr, col[:nnz].copy(), nl_row_ptr,
+                  nl_col[:nnz_nl].copy(), perm[:ns].copy(), slot_off, slot_row[:ns].copy(),
+                  slot_col[:ns].copy(), diag_slot[:nr].copy())
+
+
+def receive_buffer(values: list) -> np.ndarray:
+    """The contiguous buffer of the update procedure (Sec. 3): ranks in order,
+    each as [diag | upper | lower | interface]; lower = upper when absent."""
+    parts = []
+    for v in values:
+        up = np.asarray(v["upper"], dtype=np.float64)
+        lo = up if v.get("lower") is None else np.asarray(v["lower"], dtype=np.float64)
+        parts += [np.asarray(v["diag"], dtype=np.float64), up, lo, np.asarray(v["iface"], dtype=np.float64)]
+    return np.ascontiguousarray(np.concatenate(parts))
+
+
+def update(m: Merged, buf: np.ndarray):
+    """Reorder the buffer by P (Sec. 3, update procedure) and derive the FP32
+    copy and the Jacobi inverse diagonal.  Returns (val64, val32, dinv64, dinv32);
+    val arrays hold the local block then the non-local block."""
+    lib = loaded_library()
+    buf = np.ascontiguousarray(buf, dtype=np.float64)
+    assert buf.shape[0] == m.n_slots
+    val64 = np.zeros(max(m.n_slots, 1), np.float64)
+    val32 = np.zeros(max(m.n_slots, 1), np.float32)
+    dinv64 = np.zeros(max(m.n_rows, 1), np.float64)
+    dinv32 = np.zeros(max(m.n_rows, 1), np.float32)
+    lib.or_update(m.n_rows, m.n_slots, m.perm if m.n_slots else np.zeros(1, np.int32),
+                  m.diag_slot if m.n_rows else np.zeros(1, np.int32),
+                  buf if m.n_slots else np.zeros(1), val64, val32, dinv64, dinv32)
+    return val64[:m.n_slots], val32[:m.n_slots], dinv64[:m.n_rows], dinv32[:m.n_rows]
+
+
+def spmv(m: Merged, val64: np.ndarray, x: np.ndarray) -> np.ndarray:
+    lib = loaded_library()
+    y = np.zeros(max(m.n_rows, 1))
+    lib.or_spmv(m.n_rows, m.row_ptr, _i32(m.col if m.nnz_local else np.zeros(1)),
+                np.ascontiguousarray(val64[:max(m.nnz_local, 1)], dtype=np.float64) if m.nnz_local else np.zeros(1),
+                np.ascontiguousarray(x, dtype=np.float64) if m.n_rows else np.zeros(1), y)
+    return y[:m.n_rows]
+
+
+def true_relres(m: Merged, val64, b, x) -> float:
+    lib = loaded_library()
+    return float(lib.or_true_relres(m.n_rows, m.row_ptr, _i32(m.col),
+                                    np.ascontiguousarray(val64[:m.nnz_local], dtype=np.float64),
+                                    np.ascontiguousarray(b, dtype=np.float64),
+                                    np.ascontiguousarray(x, dtype=np.float64)))
+
+
+def pcg(m: Merged, val64, b, x0=None, tol=1e-8, max_iter=100000, max_restarts=5):
+    """Jacobi-preconditioned CG (the CG of Sec. 4, M = diag(A)).  Returns
+    (x, status, iterations, restarts, true relative residual)."""
+    lib = loaded_library()
+    if m.nnz_nonlocal:
+        raise OracleError(-5, "pcg (non-local block present)")
+    x = np.zeros(m.n_rows) if x0 is None else np.array(x0, dtype=np.float64)
+    out = np.zeros(2, np.int64)
+    res = np.zeros(1)
+    st = lib.or_pcg(m.n_rows, m.row_ptr, _i32(m.col), np.ascontiguousarray(val64[:m.nnz_local], dtype=np.float64),
+                    np.ascontiguousarray(b, dtype=np.float64), x, float(tol), int(max_iter), int(max_restarts),
+                    out, res)
+    return x, int(st), int(out[0]), int(out[1]), float(res[0])
+
+
+def value_grad(m: Merged, lam, x) -> np.ndarray:
+    """dL/dv_k = -lambda_row(k) x_col(k) for every receive-buffer slot."""
+    lib = loaded_library()
+    g = np.zeros(max(m.n_slots, 1))
+    lib.or_value_grad(m.n_slots, m.slot_row, m.slot_col, m.lo, m.n_rows,
+                      np.ascontiguousarray(lam, dtype=np.float64), np.ascontiguousarray(x, dtype=np.float64), g)
+    return g[:m.n_slots]
+
+
+def face_grad(row_a, row_b, lam, x) -> np.ndarray:
+    """dL/dc_f for face coefficients (interior: -(l_a-l_b)(x_a-x_b); wall: -l_a x_a)."""
+    lib = loaded_library()
+    row_a = np.ascontiguousarray(row_a, dtype=np.int64)
+    row_b = np.ascontiguousarray(row_b, dtype=np.int64)
+    g = np.zeros(max(row_a.shape[0], 1))
+    lib.or_face_grad(row_a.shape[0], row_a, row_b, np.ascontiguousarray(lam, dtype=np.float64),
+                     np.ascontiguousarray(x, dtype=np.float64), g)
+    return g[:row_a.shape[0]]

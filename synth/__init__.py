@@ -1,0 +1,14 @@
+"""Seeded synthetic inputs (meshes, rank decompositions, LDU coefficients).
+
+Shared by the oracle and the GPU path as input only; holds none of the
+repartitioning, update or solver arithmetic.
+"""
+from .mesh import (Mesh, Partition, LduValues, structured_mesh, stretched_dz,
+                   decompose_blocks, decompose_rcb, partition, cell_diagonal, ldu_values)
+from .workloads import RECIPES, Recipe, Workload, build, small
+
+__all__ = [
+    "Mesh", "Partition", "LduValues", "structured_mesh", "stretched_dz",
+    "decompose_blocks", "decompose_rcb", "partition", "cell_diagonal", "ldu_values",
+    "RECIPES", "Recipe", "Workload", "build", "small",
+]
