@@ -1,0 +1,208 @@
+/*
+ * rp.h - C ABI of librp.so: matrix repartitioning and Jacobi-PCG on one MI355X.
+ *
+ * Method (Olenik, Koch, Anzt, "Investigating Matrix Repartitioning to Address
+ * the Over- and Undersubscription Challenge for a GPU-based CFD Solver"):
+ *  - Sec. 3, repartitioning: GPU part k owns the rows of the alpha CPU ranks
+ *    alpha*k .. alpha*k+alpha-1 (blockwise map).  Their LDU sparsity patterns,
+ *    including the processor-interface couplings, are fused once into one
+ *    row-major (CSR) pattern; couplings whose partner row is now on the same
+ *    part are localised, the rest form a non-local block.  The fusion yields
+ *    the pattern, the update pattern U (where each rank's coefficients land in
+ *    a contiguous receive buffer) and the permutation P (buffer order -> CSR
+ *    order).
+ *  - Sec. 3, update procedure: pattern and values are separate; every
+ *    timestep each rank's coefficients go into the receive buffer, ordered by
+ *    originating rank and LDU order, and are reordered by P into the matrix.
+ *  - Sec. 4: the pressure system is solved with CG on the GPU; here with a
+ *    Jacobi preconditioner, in FP64 or as FP32-inner / FP64-outer iterative
+ *    refinement, plus the adjoint (transposed) solve and value gradients.
+ *
+ * Conventions used by every call:
+ *  - Integers are int32 unless stated; every call returns an int status.
+ *  - "Device pointer" = memory from hipMalloc on the plan's GPU; "host or
+ *    device" = either (resolved through HIP's unified addressing).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is enqueued in stream order; calls that must read results on the
+ *    host (plan creation, solve, get_*) synchronise that stream themselves.
+ *  - No call throws; on failure the status is negative and rp_last_error()
+ *    returns a message for the calling thread.
+ *  - A plan is not thread-safe; distinct plans are independent.
+ *
+ * LDU layout (the paper names the LDU host format without defining it):
+ *   A(owner[f], neighbour[f]) = upper[f], A(neighbour[f], owner[f]) = lower[f],
+ *   A(c, c) = diag[c]; an interface value is the matrix entry A(row, col) of
+ *   this rank's row.  Rank r's global rows are [off_r, off_r + n_cells_r),
+ *   off_r = sum of n_cells over ranks below r.
+ *
+ * Receive-buffer ("slot") order, the order of P and of value gradients:
+ *   share ranks in order, each as [diag | upper | lower | interface].
+ * CSR order: rows ascending, columns ascending within a row.
+ */
+#ifndef RP_H
+#define RP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define RP_OK 0
+#define RP_NOT_CONVERGED 1        /* iteration budget spent; x holds the last iterate */
+#define RP_ERR_ARG (-1)           /* bad count, null pointer, share outside the ranks */
+#define RP_ERR_MESH (-2)          /* addressing out of range, owner == neighbour,
+                                     duplicate matrix entry, unpaired interface */
+#define RP_ERR_OVERFLOW (-3)      /* rows or slots of the share reach 2^31 */
+#define RP_ERR_HIP (-4)           /* a HIP runtime call failed */
+#define RP_ERR_UNSUPPORTED (-5)   /* solve with a non-empty non-local block or a
+                                     non-symmetric matrix */
+#define RP_ERR_BREAKDOWN (-6)     /* CG breakdown: p.Ap <= 0 or not finite */
+#define RP_ERR_VALUE (-7)         /* an updated value is not finite, or diag <= 0 */
+
+/* ---- precisions -------------------------------------------------------- */
+#define RP_FP64 0                 /* FP64 everywhere */
+#define RP_MIXED 1                /* FP32 inner PCG, FP64 refinement (solve only) */
+#define RP_FP32 2                 /* FP32 matrix and vectors (rp_spmv only) */
+
+typedef struct rp_plan rp_plan;
+
+/* One CPU rank's LDU addressing (Sec. 3, step 1: the pattern including the
+ * coupling terms to non-local entries).  All arrays are host memory, owned by
+ * the caller and only read during rp_plan_create. */
+typedef struct rp_rank_desc {
+    int32_t n_cells;                 /* rows of this rank */
+    int32_t n_faces;                 /* internal faces */
+    const int32_t* owner;            /* [n_faces] local cell of the upper entry's row */
+    const int32_t* neighbour;        /* [n_faces] local cell of the upper entry's column */
+    int32_t n_iface;                 /* processor-interface couplings */
+    const int32_t* iface_cell;       /* [n_iface] local cell on this rank (the row) */
+    const int32_t* iface_nbr_rank;   /* [n_iface] rank owning the cell across the face */
+    const int32_t* iface_nbr_cell;   /* [n_iface] that cell's local id on its rank (the column) */
+} rp_rank_desc;
+
+typedef struct rp_solve_opts {
+    double tol;              /* stop when ||b - A x||_2 <= tol ||b||_2 (default 1e-8) */
+    double inner_tol;        /* RP_MIXED: inner FP32 relative tolerance (default 1e-4) */
+    int32_t max_iter;        /* FP64: CG iterations; RP_MIXED: total inner iterations */
+    int32_t precision;       /* RP_FP64 or RP_MIXED */
+    int32_t max_outer;       /* RP_MIXED: refinement steps (default 50) */
+    int32_t check_every;     /* host reads the device convergence state every this
+                                many iterations (default 32); iteration counts do
+                                not depend on it */
+    int32_t x0_zero;         /* 1: start from x = 0 and ignore x on entry */
+    int32_t max_restarts;    /* FP64: restarts when the recurrence residual passes
+                                but the true residual does not (default 5) */
+} rp_solve_opts;
+
+typedef struct rp_solve_info {
+    int32_t status;          /* the returned status */
+    int32_t iters;           /* FP64 CG iterations, or total inner FP32 iterations */
+    int32_t outer_iters;     /* RP_MIXED refinement steps (0 for RP_FP64) */
+    int32_t restarts;        /* true-residual restarts */
+    double rel_res;          /* ||b - A x||_2 / ||b||_2 at exit, FP64 on the GPU */
+} rp_solve_info;
+
+/* ---- plan (Sec. 3: steps 1-3 and the three resulting structures) ------- *
+ * Fuse ranks first_rank .. first_rank+alpha-1 of n_ranks_total CPU ranks.
+ * n_cells_all[n_ranks_total]: rows of every rank (host).  share[alpha]: the
+ * addressing of the fused ranks.  Builds pattern, U and P on the current HIP
+ * device and allocates the matrix and solver workspace there.  Validation:
+ * every index in range, owner != neighbour, no matrix entry twice, every
+ * interface coupling (c, q, d) on rank p with q in the share matched by
+ * (d, p, c) on rank q.  *out receives the plan, or NULL on failure. */
+int rp_plan_create(int32_t n_ranks_total, const int32_t* n_cells_all, int32_t first_rank,
+                   int32_t alpha, const rp_rank_desc* share, rp_plan** out);
+
+void rp_plan_destroy(rp_plan* plan);
+
+/* Sizes: rows, local and non-local entries, slots (= buffer length).
+ * slot_off[alpha+1] (nullable): buffer offset of each share rank's slot block
+ * (the update pattern U).  Any output pointer may be NULL. */
+int rp_plan_sizes(const rp_plan* plan, int64_t* n_rows, int64_t* nnz_local,
+                  int64_t* nnz_nonlocal, int64_t* n_slots, int64_t* slot_off);
+
+/* Copy the fused pattern to caller-allocated host buffers (any may be NULL):
+ * row_ptr[n_rows+1], col[nnz_local] (local column ids), perm[n_slots] (P:
+ * slot -> CSR position; non-local slots map to nnz_local + their position in
+ * the non-local block), nl_row_ptr[n_rows+1], nl_col[nnz_nonlocal] (global
+ * column ids, int64). */
+int rp_plan_get_csr(rp_plan* plan, int32_t* row_ptr, int32_t* col, int32_t* perm,
+                    int32_t* nl_row_ptr, int64_t* nl_col);
+
+/* Copy the current values to caller-allocated host buffers (any may be NULL):
+ * val64[n_slots], val32[n_slots] (CSR order, local block then non-local),
+ * dinv64[n_rows] = 1/diag, dinv32[n_rows].  Synchronises the plan. */
+int rp_plan_get_values(rp_plan* plan, double* val64, float* val32, double* dinv64,
+                       float* dinv32);
+
+/* ---- update (Sec. 3, update procedure) --------------------------------- *
+ * diag/upper/lower/iface: arrays of alpha pointers (host array), pointer s
+ * giving rank first_rank+s's values in its LDU order (host or device memory).
+ * lower == NULL means symmetric (lower = upper).  Stages the values into the
+ * receive buffer at U's offsets (host memory: per-rank copies; device
+ * memory: one staging kernel) and reorders them by P into the FP64 matrix,
+ * its FP32 copy (round to nearest even) and the Jacobi inverse diagonal
+ * (one IEEE division, then rounded to FP32).  Asynchronous on `stream`: the
+ * inputs must stay unchanged until the stream has passed this call.  A value
+ * that is not finite or a diagonal <= 0 is recorded on the device and
+ * reported as RP_ERR_VALUE by the next rp_sync / rp_solve. */
+int rp_update_values(rp_plan* plan, const double* const* diag, const double* const* upper,
+                     const double* const* lower, const double* const* iface, void* stream);
+
+/* Same as rp_update_values with the receive buffer already filled by the
+ * caller: slots[n_slots] is a device array in slot order (the buffer that
+ * ranks write straight into when they can reach device memory). */
+int rp_update_values_slots(rp_plan* plan, const double* slots, void* stream);
+
+/* ---- kernels on the fused matrix ---------------------------------------- *
+ * y = A x over the local block, x and y device arrays of n_rows elements:
+ * double with RP_FP64, float with RP_FP32.  Each row is summed from 0 in
+ * column order with one rounding per product and per sum. */
+int rp_spmv(rp_plan* plan, int32_t precision, const void* x, void* y, void* stream);
+
+/* ---- solve (Sec. 4: CG for the pressure system) ------------------------ *
+ * b, x: device arrays of n_rows doubles in fused row order (the share's
+ * ranks in order, each in local cell order).  x holds x0 on entry (unless
+ * opts->x0_zero) and the solution on return.  opts NULL = defaults.  Blocks
+ * until the solve is finished.  Returns RP_OK, RP_NOT_CONVERGED,
+ * RP_ERR_BREAKDOWN, RP_ERR_UNSUPPORTED (non-local block or non-symmetric
+ * matrix), RP_ERR_VALUE (a pending update error).  b = 0 gives x = 0. */
+int rp_solve(rp_plan* plan, const double* b, double* x, const rp_solve_opts* opts,
+             rp_solve_info* info, void* stream);
+
+void rp_solve_opts_default(rp_solve_opts* opts);
+
+/* ---- adjoint -------------------------------------------------------------- *
+ * Gradient of a loss L with respect to every receive-buffer slot, given the
+ * forward solution x and lambda = A^-T dL/dx (for symmetric A, one more
+ * rp_solve): g_slots[k] = -lambda[row(k)] * x[col(k)] (device arrays).  Under
+ * the symmetric convention the caller adds the upper and lower slot
+ * gradients of a face. */
+int rp_value_grad(rp_plan* plan, const double* lambda, const double* x, double* g_slots,
+                  void* stream);
+
+/* ---- lifetime / diagnostics --------------------------------------------- */
+/* Wait for the plan's pending work; reports a pending RP_ERR_VALUE. */
+int rp_sync(rp_plan* plan);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char* rp_last_error(void);
+
+/* Kernel timing with HIP events on the launch stream (off by default).  While
+ * enabled, every launch of kernel `kernel` (RP_KERNEL_*) is bracketed by an
+ * event pair; rp_plan_kernel_stats returns the launch count and the summed
+ * device time since enabling. */
+#define RP_KERNEL_SPMV64 0        /* FP64 CSR SpMV inside CG (q = A p with p.q) */
+#define RP_KERNEL_SPMV32 1        /* FP32 CSR SpMV inside the inner CG */
+#define RP_KERNEL_SCATTER 2       /* value update (reorder by P) */
+#define RP_N_KERNELS 3
+int rp_plan_set_timing(rp_plan* plan, int32_t enable);
+int rp_plan_kernel_stats(rp_plan* plan, int32_t kernel, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RP_H */

@@ -1,0 +1,440 @@
+// extern "C" entry points of librp (declared in include/rp.h): argument
+// checks, allocation, stream plumbing and error reporting around the
+// kernels.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "rp_internal.hpp"
+
+namespace rp {
+
+namespace {
+thread_local char g_err[1024] = "";
+}
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = 0; }
+
+int timing_begin(rp_plan* p, int kernel, hipStream_t s) {
+    if (!p->timing.enabled) return RP_OK;
+    EventPool& e = p->timing.pool[kernel];
+    if (e.used == (int64_t)e.start.size()) {
+        hipEvent_t a, b;
+        RP_HIP_TRY(hipEventCreate(&a));
+        RP_HIP_TRY(hipEventCreate(&b));
+        e.start.push_back(a);
+        e.stop.push_back(b);
+    }
+    RP_HIP_TRY(hipEventRecord(e.start[e.used], s));
+    return RP_OK;
+}
+
+int timing_end(rp_plan* p, int kernel, hipStream_t s) {
+    if (!p->timing.enabled) return RP_OK;
+    EventPool& e = p->timing.pool[kernel];
+    RP_HIP_TRY(hipEventRecord(e.stop[e.used], s));
+    ++e.used;
+    return RP_OK;
+}
+
+int timing_collect(rp_plan* p, int kernel, int64_t keep) {
+    EventPool& e = p->timing.pool[kernel];
+    if (!p->timing.enabled || e.used == 0) {
+        e.used = 0;
+        return RP_OK;
+    }
+    keep = std::min<int64_t>(std::max<int64_t>(keep, 0), e.used);
+    for (int64_t i = 0; i < keep; ++i) {
+        float ms = 0.f;
+        RP_HIP_TRY(hipEventSynchronize(e.stop[i]));
+        RP_HIP_TRY(hipEventElapsedTime(&ms, e.start[i], e.stop[i]));
+        p->timing.launches[kernel] += 1;
+        p->timing.total_ms[kernel] += ms;
+    }
+    e.used = 0;
+    return RP_OK;
+}
+
+namespace {
+
+void free_plan(rp_plan* p) {
+    if (!p) return;
+    void* dev[] = {p->d_slot_off, p->d_row0, p->d_nf, p->d_face_off, p->d_iface_off, p->d_row_ptr, p->d_col,
+                   p->d_perm, p->d_perm_inv, p->d_nl_row_ptr, p->d_nl_col, p->d_iface_partner, p->d_recv,
+                   p->d_val64, p->d_val32, p->d_dinv64, p->d_dinv32, p->d_r, p->d_p, p->d_q, p->d_r32,
+                   p->d_p32, p->d_q32, p->d_x32, p->d_partials, p->d_st64, p->d_st32, p->d_st_outer,
+                   p->d_flags};
+    for (void* q : dev)
+        if (q) (void)hipFree(q);
+    if (p->h_st64) (void)hipHostFree(p->h_st64);
+    if (p->h_st32) (void)hipHostFree(p->h_st32);
+    if (p->h_flags) (void)hipHostFree(p->h_flags);
+    for (auto& e : p->timing.pool) {
+        for (hipEvent_t ev : e.start) (void)hipEventDestroy(ev);
+        for (hipEvent_t ev : e.stop) (void)hipEventDestroy(ev);
+    }
+    delete p;
+}
+
+template <typename T>
+int dalloc(T** q, int64_t count) {
+    RP_HIP_TRY(hipMalloc(q, sizeof(T) * (size_t)std::max<int64_t>(count, 1)));
+    return RP_OK;
+}
+
+int alloc_values(rp_plan* p) {
+    const int64_t n = p->n_rows, ns = p->n_slots;
+    RP_TRY(dalloc(&p->d_recv, ns));
+    RP_TRY(dalloc(&p->d_val64, ns));
+    RP_TRY(dalloc(&p->d_val32, ns));
+    RP_TRY(dalloc(&p->d_dinv64, n));
+    RP_TRY(dalloc(&p->d_dinv32, n));
+    RP_TRY(dalloc(&p->d_r, n));
+    RP_TRY(dalloc(&p->d_p, n));
+    RP_TRY(dalloc(&p->d_q, n));
+    RP_TRY(dalloc(&p->d_r32, n));
+    RP_TRY(dalloc(&p->d_p32, n));
+    RP_TRY(dalloc(&p->d_q32, n));
+    RP_TRY(dalloc(&p->d_x32, n));
+    RP_HIP_TRY(hipMalloc(&p->d_partials, sizeof(double) * 2 * MAX_PARTIALS));
+    RP_TRY(dalloc(&p->d_st64, 1));
+    RP_TRY(dalloc(&p->d_st32, 1));
+    RP_TRY(dalloc(&p->d_st_outer, 1));
+    RP_HIP_TRY(hipMemset(p->d_st64, 0, sizeof(CgState<double>)));
+    RP_HIP_TRY(hipMemset(p->d_st32, 0, sizeof(CgState<float>)));
+    RP_HIP_TRY(hipMemset(p->d_st_outer, 0, sizeof(CgState<double>)));
+    RP_HIP_TRY(hipHostMalloc((void**)&p->h_st64, sizeof(CgState<double>), hipHostMallocDefault));
+    RP_HIP_TRY(hipHostMalloc((void**)&p->h_st32, sizeof(CgState<float>), hipHostMallocDefault));
+    RP_HIP_TRY(hipHostMalloc((void**)&p->h_flags, 2 * sizeof(uint32_t), hipHostMallocDefault));
+    return RP_OK;
+}
+
+// true when ptr is device memory (hipMalloc) reachable from the plan's GPU
+bool is_device_ptr(const void* ptr) {
+    hipPointerAttribute_t a;
+    std::memset(&a, 0, sizeof(a));
+    if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int activate(rp_plan* p) {
+    int cur = -1;
+    RP_HIP_TRY(hipGetDevice(&cur));
+    if (cur != p->device) RP_HIP_TRY(hipSetDevice(p->device));
+    return RP_OK;
+}
+
+#define RP_CHECK(cond, code, ...)       \
+    do {                                \
+        if (!(cond)) {                  \
+            ::rp::set_error(__VA_ARGS__); \
+            return (code);              \
+        }                               \
+    } while (0)
+
+int create(int32_t n_ranks_total, const int32_t* n_cells_all, int32_t first, int32_t alpha,
+           const rp_rank_desc* share, rp_plan** out) {
+    RP_CHECK(out != nullptr, RP_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    RP_CHECK(n_ranks_total >= 1 && n_cells_all != nullptr, RP_ERR_ARG, "need n_ranks_total >= 1 and n_cells_all");
+    RP_CHECK(alpha >= 1 && first >= 0 && (int64_t)first + alpha <= n_ranks_total, RP_ERR_ARG,
+             "share [%d, %d + %d) is not inside the %d ranks", first, first, alpha, n_ranks_total);
+    RP_CHECK(share != nullptr, RP_ERR_ARG, "share is NULL");
+
+    std::unique_ptr<rp_plan, void (*)(rp_plan*)> p(new (std::nothrow) rp_plan(), free_plan);
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "out of host memory");
+    RP_HIP_TRY(hipGetDevice(&p->device));
+    p->n_ranks_total = n_ranks_total;
+    p->first = first;
+    p->alpha = alpha;
+    p->off_all.assign(n_ranks_total + 1, 0);
+    for (int32_t r = 0; r < n_ranks_total; ++r) {
+        RP_CHECK(n_cells_all[r] >= 0, RP_ERR_ARG, "n_cells_all[%d] < 0", r);
+        p->off_all[r + 1] = p->off_all[r] + n_cells_all[r];
+    }
+    int64_t slots = 0, rows = 0, ifaces = 0;
+    p->slot_off.assign(alpha + 1, 0);
+    p->row0.assign(alpha + 1, 0);
+    p->iface_off.assign(alpha + 1, 0);
+    for (int32_t s = 0; s < alpha; ++s) {
+        const rp_rank_desc& d = share[s];
+        RP_CHECK(d.n_cells == n_cells_all[first + s], RP_ERR_ARG,
+                 "share[%d].n_cells = %d but n_cells_all[%d] = %d", s, d.n_cells, first + s,
+                 n_cells_all[first + s]);
+        RP_CHECK(d.n_faces >= 0 && d.n_iface >= 0, RP_ERR_ARG, "share[%d]: negative count", s);
+        RP_CHECK(d.n_faces == 0 || (d.owner && d.neighbour), RP_ERR_ARG, "share[%d]: owner/neighbour NULL", s);
+        RP_CHECK(d.n_iface == 0 || (d.iface_cell && d.iface_nbr_rank && d.iface_nbr_cell), RP_ERR_ARG,
+                 "share[%d]: interface arrays NULL", s);
+        slots += (int64_t)d.n_cells + 2 * (int64_t)d.n_faces + d.n_iface;
+        rows += d.n_cells;
+        ifaces += d.n_iface;
+        RP_CHECK(slots < INT32_MAX && rows < INT32_MAX && ifaces < INT32_MAX, RP_ERR_OVERFLOW,
+                 "the share's rows or slots reach 2^31");
+        p->slot_off[s + 1] = (int32_t)slots;
+        p->row0[s + 1] = (int32_t)rows;
+        p->iface_off[s + 1] = (int32_t)ifaces;
+        p->n_cells.push_back(d.n_cells);
+        p->n_faces.push_back(d.n_faces);
+        p->n_iface.push_back(d.n_iface);
+    }
+    p->n_rows = rows;
+    p->n_slots = slots;
+    RP_TRY(plan_build(p.get(), share));
+    RP_TRY(alloc_values(p.get()));
+    p->h_src.assign(4 * (size_t)alpha, nullptr);
+    *out = p.release();
+    return RP_OK;
+}
+
+int update(rp_plan* p, const double* const* diag, const double* const* upper, const double* const* lower,
+           const double* const* iface, hipStream_t s) {
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    RP_CHECK(diag && upper && iface, RP_ERR_ARG, "diag/upper/iface pointer arrays are NULL");
+    RP_TRY(activate(p));
+    bool all_device = true;
+    for (int32_t i = 0; i < p->alpha; ++i) {
+        RP_CHECK(p->n_cells[i] == 0 || diag[i], RP_ERR_ARG, "diag[%d] is NULL", i);
+        RP_CHECK(p->n_faces[i] == 0 || upper[i], RP_ERR_ARG, "upper[%d] is NULL", i);
+        RP_CHECK(p->n_faces[i] == 0 || !lower || lower[i], RP_ERR_ARG, "lower[%d] is NULL", i);
+        RP_CHECK(p->n_iface[i] == 0 || iface[i], RP_ERR_ARG, "iface[%d] is NULL", i);
+        const double* ptrs[4] = {diag[i], upper[i], lower ? lower[i] : nullptr, iface[i]};
+        for (const double* q : ptrs)
+            if (q && !is_device_ptr(q)) all_device = false;
+        p->h_src[4 * i + 0] = diag[i];
+        p->h_src[4 * i + 1] = upper[i];
+        p->h_src[4 * i + 2] = lower ? lower[i] : upper[i];
+        p->h_src[4 * i + 3] = iface[i];
+    }
+    RP_HIP_TRY(hipMemsetAsync(p->d_flags, 0, 2 * sizeof(uint32_t), s));
+    if (all_device) {
+        RP_TRY(launch_stage_table(p, lower != nullptr, s));
+    } else {
+        // host-buffer path: one copy per rank array into the receive buffer at U's offsets
+        for (int32_t i = 0; i < p->alpha; ++i) {
+            double* dst = p->d_recv + p->slot_off[i];
+            const size_t nc = p->n_cells[i], nf = p->n_faces[i], ni = p->n_iface[i];
+            if (nc) RP_HIP_TRY(hipMemcpyAsync(dst, diag[i], nc * 8, hipMemcpyDefault, s));
+            if (nf) RP_HIP_TRY(hipMemcpyAsync(dst + nc, upper[i], nf * 8, hipMemcpyDefault, s));
+            if (nf) RP_HIP_TRY(hipMemcpyAsync(dst + nc + nf, lower ? lower[i] : upper[i], nf * 8,
+                                              hipMemcpyDefault, s));
+            if (ni) RP_HIP_TRY(hipMemcpyAsync(dst + nc + 2 * nf, iface[i], ni * 8, hipMemcpyDefault, s));
+        }
+    }
+    RP_TRY(launch_symmetry_check(p, p->d_recv, lower != nullptr, s));
+    RP_TRY(launch_update(p, p->d_recv, s));
+    p->has_values = true;
+    p->last_stream = s;
+    return RP_OK;
+}
+
+}  // namespace
+}  // namespace rp
+
+using namespace rp;
+
+extern "C" {
+
+int rp_plan_create(int32_t n_ranks_total, const int32_t* n_cells_all, int32_t first_rank, int32_t alpha,
+                   const rp_rank_desc* share, rp_plan** out) {
+    clear_error();
+    try {
+        return create(n_ranks_total, n_cells_all, first_rank, alpha, share, out);
+    } catch (const std::bad_alloc&) {
+        set_error("out of host memory");
+        return RP_ERR_ARG;
+    }
+}
+
+void rp_plan_destroy(rp_plan* plan) {
+    if (!plan) return;
+    (void)hipDeviceSynchronize();
+    free_plan(plan);
+}
+
+int rp_plan_sizes(const rp_plan* p, int64_t* n_rows, int64_t* nnz_local, int64_t* nnz_nonlocal,
+                  int64_t* n_slots, int64_t* slot_off) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    if (n_rows) *n_rows = p->n_rows;
+    if (nnz_local) *nnz_local = p->nnz;
+    if (nnz_nonlocal) *nnz_nonlocal = p->nnz_nl;
+    if (n_slots) *n_slots = p->n_slots;
+    if (slot_off)
+        for (int32_t i = 0; i <= p->alpha; ++i) slot_off[i] = p->slot_off[i];
+    return RP_OK;
+}
+
+int rp_plan_get_csr(rp_plan* p, int32_t* row_ptr, int32_t* col, int32_t* perm, int32_t* nl_row_ptr,
+                    int64_t* nl_col) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    RP_TRY(activate(p));
+    RP_HIP_TRY(hipDeviceSynchronize());
+    if (row_ptr) RP_HIP_TRY(hipMemcpy(row_ptr, p->d_row_ptr, 4 * (p->n_rows + 1), hipMemcpyDeviceToHost));
+    if (col && p->nnz) RP_HIP_TRY(hipMemcpy(col, p->d_col, 4 * p->nnz, hipMemcpyDeviceToHost));
+    if (perm && p->n_slots) RP_HIP_TRY(hipMemcpy(perm, p->d_perm, 4 * p->n_slots, hipMemcpyDeviceToHost));
+    if (nl_row_ptr)
+        RP_HIP_TRY(hipMemcpy(nl_row_ptr, p->d_nl_row_ptr, 4 * (p->n_rows + 1), hipMemcpyDeviceToHost));
+    if (nl_col && p->nnz_nl) RP_HIP_TRY(hipMemcpy(nl_col, p->d_nl_col, 8 * p->nnz_nl, hipMemcpyDeviceToHost));
+    return RP_OK;
+}
+
+int rp_plan_get_values(rp_plan* p, double* val64, float* val32, double* dinv64, float* dinv32) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    RP_CHECK(p->has_values, RP_ERR_ARG, "no values yet: call rp_update_values first");
+    RP_TRY(activate(p));
+    RP_HIP_TRY(hipDeviceSynchronize());
+    if (val64 && p->n_slots) RP_HIP_TRY(hipMemcpy(val64, p->d_val64, 8 * p->n_slots, hipMemcpyDeviceToHost));
+    if (val32 && p->n_slots) RP_HIP_TRY(hipMemcpy(val32, p->d_val32, 4 * p->n_slots, hipMemcpyDeviceToHost));
+    if (dinv64 && p->n_rows) RP_HIP_TRY(hipMemcpy(dinv64, p->d_dinv64, 8 * p->n_rows, hipMemcpyDeviceToHost));
+    if (dinv32 && p->n_rows) RP_HIP_TRY(hipMemcpy(dinv32, p->d_dinv32, 4 * p->n_rows, hipMemcpyDeviceToHost));
+    return RP_OK;
+}
+
+int rp_update_values(rp_plan* p, const double* const* diag, const double* const* upper,
+                     const double* const* lower, const double* const* iface, void* stream) {
+    clear_error();
+    return update(p, diag, upper, lower, iface, as_stream(stream));
+}
+
+int rp_update_values_slots(rp_plan* p, const double* slots, void* stream) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    RP_CHECK(slots != nullptr || p->n_slots == 0, RP_ERR_ARG, "slots is NULL");
+    RP_TRY(activate(p));
+    hipStream_t s = as_stream(stream);
+    RP_HIP_TRY(hipMemsetAsync(p->d_flags, 0, 2 * sizeof(uint32_t), s));
+    RP_TRY(launch_symmetry_check(p, slots, true, s));
+    RP_TRY(launch_update(p, slots, s));
+    p->has_values = true;
+    p->last_stream = s;
+    return RP_OK;
+}
+
+int rp_spmv(rp_plan* p, int32_t precision, const void* x, void* y, void* stream) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    RP_CHECK(p->has_values, RP_ERR_ARG, "no values yet: call rp_update_values first");
+    RP_CHECK(p->n_rows == 0 || (x && y), RP_ERR_ARG, "x or y is NULL");
+    RP_CHECK(precision == RP_FP64 || precision == RP_FP32, RP_ERR_ARG, "precision must be RP_FP64 or RP_FP32");
+    RP_TRY(activate(p));
+    if (precision == RP_FP64)
+        return launch_spmv64(p, static_cast<const double*>(x), static_cast<double*>(y), as_stream(stream));
+    return launch_spmv32(p, static_cast<const float*>(x), static_cast<float*>(y), as_stream(stream));
+}
+
+void rp_solve_opts_default(rp_solve_opts* o) {
+    if (!o) return;
+    o->tol = 1e-8;
+    o->inner_tol = 1e-4;
+    o->max_iter = 100000;
+    o->precision = RP_FP64;
+    o->max_outer = 50;
+    o->check_every = 32;
+    o->x0_zero = 0;
+    o->max_restarts = 5;
+}
+
+int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, rp_solve_info* info,
+             void* stream) {
+    clear_error();
+    rp_solve_info local_info;
+    std::memset(&local_info, 0, sizeof(local_info));
+    rp_solve_info& inf = info ? *info : local_info;
+    std::memset(&inf, 0, sizeof(inf));
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    rp_solve_opts o;
+    rp_solve_opts_default(&o);
+    if (opts) o = *opts;
+    RP_CHECK(p->n_rows == 0 || (b && x), RP_ERR_ARG, "b or x is NULL");
+    RP_CHECK(o.tol >= 0.0 && o.inner_tol > 0.0 && o.inner_tol < 1.0 && o.max_iter >= 0 && o.max_outer >= 0 &&
+                 o.max_restarts >= 0,
+             RP_ERR_ARG, "bad solve options");
+    RP_CHECK(o.precision == RP_FP64 || o.precision == RP_MIXED, RP_ERR_ARG,
+             "precision must be RP_FP64 or RP_MIXED");
+    RP_TRY(activate(p));
+    hipStream_t s = as_stream(stream);
+    p->last_stream = s;
+    int rc;
+    if (p->n_rows == 0) {
+        rc = RP_OK;
+    } else if (o.precision == RP_FP64) {
+        rc = solve_fp64(p, b, x, o, inf, s);
+    } else {
+        rc = solve_mixed(p, b, x, o, inf, s);
+    }
+    inf.status = rc;
+    return rc;
+}
+
+int rp_value_grad(rp_plan* p, const double* lambda, const double* x, double* g_slots, void* stream) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    RP_CHECK(p->n_rows == 0 || (lambda && x && g_slots), RP_ERR_ARG, "lambda, x or g_slots is NULL");
+    RP_CHECK(p->nnz_nl == 0, RP_ERR_UNSUPPORTED, "value gradients need a share without non-local entries");
+    RP_TRY(activate(p));
+    return launch_value_grad(p, lambda, x, g_slots, as_stream(stream));
+}
+
+int rp_sync(rp_plan* p) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    RP_TRY(activate(p));
+    hipStream_t s = p->last_stream;
+    RP_HIP_TRY(hipStreamSynchronize(s));
+    RP_TRY(timing_collect(p, RP_KERNEL_SCATTER, INT64_MAX));
+    RP_HIP_TRY(hipMemcpy(p->h_flags, p->d_flags, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (p->h_flags[0] & FLAG_VALUE) {
+        set_error("the last update produced a value that is not finite or a diagonal <= 0");
+        return RP_ERR_VALUE;
+    }
+    return RP_OK;
+}
+
+const char* rp_last_error(void) { return g_err; }
+
+int rp_plan_set_timing(rp_plan* p, int32_t enable) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    RP_TRY(activate(p));
+    RP_HIP_TRY(hipDeviceSynchronize());
+    p->timing.enabled = enable != 0;
+    for (int k = 0; k < RP_N_KERNELS; ++k) {
+        p->timing.launches[k] = 0;
+        p->timing.total_ms[k] = 0.0;
+        p->timing.pool[k].used = 0;
+    }
+    return RP_OK;
+}
+
+int rp_plan_kernel_stats(rp_plan* p, int32_t kernel, int64_t* launches, double* total_ms) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    RP_CHECK(kernel >= 0 && kernel < RP_N_KERNELS, RP_ERR_ARG, "unknown kernel id %d", kernel);
+    RP_TRY(activate(p));
+    RP_HIP_TRY(hipDeviceSynchronize());
+    RP_TRY(timing_collect(p, kernel, INT64_MAX));
+    if (launches) *launches = p->timing.launches[kernel];
+    if (total_ms) *total_ms = p->timing.total_ms[kernel];
+    return RP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,203 @@
+// Internal declarations of librp: the plan object, error plumbing and the
+// launchers each kernel file provides.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rp.h"
+
+namespace rp {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define RP_HIP_TRY(call)                                                          \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            ::rp::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                            __FILE__, __LINE__);                                  \
+            return RP_ERR_HIP;                                                    \
+        }                                                                         \
+    } while (0)
+
+#define RP_TRY(expr)              \
+    do {                          \
+        int rc_ = (expr);         \
+        if (rc_ != RP_OK) return rc_; \
+    } while (0)
+
+// device-side error bits (plan->d_flags[0])
+enum : uint32_t {
+    FLAG_MESH_RANGE = 1u << 0,     // owner/neighbour/interface index out of range
+    FLAG_MESH_SELF = 1u << 1,      // owner == neighbour, or interface to own rank
+    FLAG_MESH_DUP = 1u << 2,       // a matrix entry addressed twice
+    FLAG_MESH_UNPAIRED = 1u << 3,  // interface coupling without its partner
+    FLAG_VALUE = 1u << 8,          // non-finite value or diag <= 0 in an update
+};
+// plan->d_flags[1]: set when the last update produced a non-symmetric matrix
+// (upper != lower, or an interface value != its partner's)
+
+// ---------------------------------------------------------------------------
+// CG state kept on the device; S is the scalar type of the iteration
+// ---------------------------------------------------------------------------
+enum : int32_t {
+    CG_RUNNING = 0,
+    CG_CONVERGED = 1,   // recurrence residual passed the threshold
+    CG_BREAKDOWN = 2,   // p.Ap <= 0 or not finite
+    CG_MAX_ITER = 3,    // iteration budget spent
+    CG_ZERO_RHS = 4,    // ||b|| = 0
+};
+
+template <typename S>
+struct CgState {
+    S rz;          // (r, z) of the current residual
+    S pq;          // (p, A p)
+    S alpha;
+    S beta;
+    S rr;          // (r, r) of the current (recurrence) residual
+    S bb;          // (b, b)
+    S thresh;      // tol^2 * bb
+    S rr_true;     // (r, r) from the last explicit residual b - A x
+    int32_t iter;  // completed iterations
+    int32_t max_iter;
+    int32_t done;  // CG_*
+    int32_t pad;
+    uint32_t counter[2];  // arrival counters of the last-block reductions
+};
+
+// kernel launch shapes
+constexpr int SPMV_BLOCK = 256;               // rows per SpMV block = threads
+constexpr int SPMV_UNROLL = 8;                // staged products per thread
+constexpr int SPMV_CAP = SPMV_UNROLL * SPMV_BLOCK;
+constexpr int VEC_BLOCK = 256;                // elementwise kernels
+constexpr int N_XCD = 8;                      // MI355X: 8 accelerator dies
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct EventPool {
+    std::vector<hipEvent_t> start, stop;
+    int64_t used = 0;
+};
+
+struct Timing {
+    bool enabled = false;
+    int64_t launches[RP_N_KERNELS] = {0, 0, 0};
+    double total_ms[RP_N_KERNELS] = {0, 0, 0};
+    EventPool pool[RP_N_KERNELS];
+};
+
+}  // namespace rp
+
+struct rp_plan {
+    int device = 0;
+    int32_t n_ranks_total = 0, first = 0, alpha = 0;
+    int64_t n_rows = 0, n_slots = 0, nnz = 0, nnz_nl = 0, n_iface_share = 0;
+    std::vector<int64_t> off_all;    // [n_ranks_total+1] global row offsets
+    std::vector<int32_t> slot_off;   // [alpha+1] receive-buffer offsets (U)
+    std::vector<int32_t> row0;       // [alpha+1] first fused row of each share rank
+    std::vector<int32_t> n_cells, n_faces, n_iface;  // per share rank
+    std::vector<int32_t> iface_off;  // [alpha+1] offsets into the share's interfaces
+
+    // rank tables on the device
+    int32_t* d_slot_off = nullptr;   // [alpha+1]
+    int32_t* d_row0 = nullptr;       // [alpha+1]
+    int32_t* d_nf = nullptr;         // [alpha] internal faces
+    int32_t* d_face_off = nullptr;   // [alpha+1] offsets into the share's faces
+    int32_t* d_iface_off = nullptr;  // [alpha+1]
+
+    // pattern
+    int32_t* d_row_ptr = nullptr;    // [n_rows+1]
+    int32_t* d_col = nullptr;        // [nnz]
+    int32_t* d_perm = nullptr;       // [n_slots] slot -> position (P)
+    int32_t* d_perm_inv = nullptr;   // [nnz + nnz_nl] position -> slot
+    int32_t* d_nl_row_ptr = nullptr; // [n_rows+1]
+    int64_t* d_nl_col = nullptr;     // [nnz_nl]
+    int32_t* d_iface_partner = nullptr;  // [n_iface_share] partner slot, -1 if non-local
+
+    // values
+    double* d_recv = nullptr;        // [n_slots] receive buffer, slot order
+    double* d_val64 = nullptr;       // [n_slots] CSR order (local, then non-local)
+    float* d_val32 = nullptr;        // [n_slots]
+    double* d_dinv64 = nullptr;      // [n_rows]
+    float* d_dinv32 = nullptr;       // [n_rows]
+    bool has_values = false;
+
+    // staging table for device-resident per-rank values: 4*alpha pointers
+    const double** d_src = nullptr;
+    std::vector<const double*> h_src;
+
+    // solver workspace
+    double *d_r = nullptr, *d_p = nullptr, *d_q = nullptr;
+    float *d_r32 = nullptr, *d_p32 = nullptr, *d_q32 = nullptr, *d_x32 = nullptr;
+    void* d_partials = nullptr;      // [2 * max blocks] doubles
+    rp::CgState<double>* d_st64 = nullptr;
+    rp::CgState<float>* d_st32 = nullptr;
+    rp::CgState<double>* d_st_outer = nullptr;
+    rp::CgState<double>* h_st64 = nullptr;   // pinned mirrors
+    rp::CgState<float>* h_st32 = nullptr;
+    uint32_t* d_flags = nullptr;     // [2] error bits, asymmetry flag
+    uint32_t* h_flags = nullptr;     // pinned mirror
+
+    hipStream_t last_stream = nullptr;
+    rp::Timing timing;
+};
+
+namespace rp {
+
+// launch-shape helpers
+// SpMV-shaped kernels: at most SPMV_GRID_MAX blocks (a multiple of N_XCD),
+// each looping over a contiguous range of row groups.
+constexpr int SPMV_GRID_MAX = 2048;
+inline int spmv_grid(int64_t n_rows) {
+    int64_t groups = (n_rows + SPMV_BLOCK - 1) / SPMV_BLOCK;
+    int64_t g = ((groups + N_XCD - 1) / N_XCD) * N_XCD;
+    if (g < N_XCD) g = N_XCD;
+    if (g > SPMV_GRID_MAX) g = SPMV_GRID_MAX;
+    return (int)g;
+}
+// elementwise kernels: grid-stride loops over at most VEC_GRID_MAX blocks
+constexpr int VEC_GRID_MAX = 2048;
+inline int vec_grid(int64_t n) {
+    int64_t g = (n + VEC_BLOCK * 4 - 1) / (VEC_BLOCK * 4);
+    if (g < 1) g = 1;
+    if (g > VEC_GRID_MAX) g = VEC_GRID_MAX;
+    return (int)g;
+}
+// partial sums per reduction: one per block of the larger grid
+constexpr int MAX_PARTIALS = SPMV_GRID_MAX > VEC_GRID_MAX ? SPMV_GRID_MAX : VEC_GRID_MAX;
+
+// plan.hip
+int plan_build(rp_plan* p, const rp_rank_desc* share);
+// update.hip
+// src: the receive buffer in slot order (the plan's own, or the caller's)
+int launch_update(rp_plan* p, const double* src, hipStream_t s);
+int launch_symmetry_check(rp_plan* p, const double* src, bool lower_given, hipStream_t s);
+int launch_stage_table(rp_plan* p, bool lower_given, hipStream_t s);
+// spmv.hip
+int launch_spmv64(rp_plan* p, const double* x, double* y, hipStream_t s);
+int launch_spmv32(rp_plan* p, const float* x, float* y, hipStream_t s);
+// cg.hip
+int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
+               hipStream_t s);
+int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
+                hipStream_t s);
+// grad.hip
+int launch_value_grad(rp_plan* p, const double* lambda, const double* x, double* g, hipStream_t s);
+
+// timing (capi.cpp)
+int timing_begin(rp_plan* p, int kernel, hipStream_t s);
+int timing_end(rp_plan* p, int kernel, hipStream_t s);
+// fold the first `keep` pending event pairs of `kernel` into the totals and
+// drop the rest (launches that found the solve already finished)
+int timing_collect(rp_plan* p, int kernel, int64_t keep);
+
+}  // namespace rp

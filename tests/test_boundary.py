@@ -1,0 +1,115 @@
+"""The C-ABI boundary on the CPU: librp.so loads, exports every entry point
+include/rp.h declares, and the ctypes structs match the C layouts.  No GPU
+call is made here."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rp.h")
+PKG = os.path.join(ROOT, "paper_2510_08536_amd")
+
+
+@pytest.fixture(scope="module")
+def lib_path():
+    path = os.path.join(PKG, "librp.so")
+    if not os.path.exists(path):
+        import importlib.util
+        spec = importlib.util.spec_from_file_location("_rp_build", os.path.join(PKG, "_build.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.build()
+    return path
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(rp_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("rp_plan_create", "rp_update_values", "rp_solve", "rp_value_grad", "rp_plan_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib_path):
+    lib = ctypes.CDLL(lib_path)
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol(lib_path):
+    import paper_2510_08536_amd.rp as rp
+    assert sorted(rp.EXPORTED) == _declared_functions()
+
+
+def test_struct_layouts_match_header(lib_path):
+    import paper_2510_08536_amd.rp as rp
+    src = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "rp.h"
+#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m))
+int main(void) {
+  printf("rp_rank_desc %zu\n", sizeof(rp_rank_desc));
+  printf("rp_solve_opts %zu\n", sizeof(rp_solve_opts));
+  printf("rp_solve_info %zu\n", sizeof(rp_solve_info));
+  F(rp_rank_desc, n_cells); F(rp_rank_desc, n_faces); F(rp_rank_desc, owner); F(rp_rank_desc, neighbour);
+  F(rp_rank_desc, n_iface); F(rp_rank_desc, iface_cell); F(rp_rank_desc, iface_nbr_rank);
+  F(rp_rank_desc, iface_nbr_cell);
+  F(rp_solve_opts, tol); F(rp_solve_opts, inner_tol); F(rp_solve_opts, max_iter); F(rp_solve_opts, precision);
+  F(rp_solve_opts, max_outer); F(rp_solve_opts, check_every); F(rp_solve_opts, x0_zero);
+  F(rp_solve_opts, max_restarts);
+  F(rp_solve_info, status); F(rp_solve_info, iters); F(rp_solve_info, outer_iters); F(rp_solve_info, restarts);
+  F(rp_solve_info, rel_res);
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), "-o", exe, c])
+        out = subprocess.check_output([exe], text=True).split("\n")
+    got = dict(line.rsplit(" ", 1) for line in out if line)
+    for name, cls in (("rp_rank_desc", rp.rp_rank_desc), ("rp_solve_opts", rp.rp_solve_opts),
+                      ("rp_solve_info", rp.rp_solve_info)):
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert int(got[f"{name}.{field}"]) == getattr(cls, field).offset, (name, field)
+
+
+def test_opts_defaults(lib_path):
+    import paper_2510_08536_amd.rp as rp
+    o = rp.default_opts()
+    assert o.tol == 1e-8 and o.inner_tol == 1e-4 and o.precision == rp.RP_FP64 and o.check_every > 0
+
+
+def test_missing_library_fails_loudly():
+    """The package refuses to import without librp.so: there is no fallback."""
+    with tempfile.TemporaryDirectory() as d:
+        pkg = os.path.join(d, "paper_2510_08536_amd")
+        os.mkdir(pkg)
+        for f in ("__init__.py", "rp.py", "autograd.py"):
+            open(os.path.join(pkg, f), "w").write(open(os.path.join(PKG, f)).read())
+        p = subprocess.run([sys.executable, "-c", "import paper_2510_08536_amd"], cwd=d,
+                           capture_output=True, text=True)
+    assert p.returncode != 0 and "ImportError" in p.stderr and "not built" in p.stderr
+
+
+def test_product_does_not_touch_the_oracle():
+    for dirpath, _, files in os.walk(PKG):
+        if "_build" in dirpath:
+            continue
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "liboracle" not in text and "oracle.c" not in text, f
