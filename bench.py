@@ -1,0 +1,275 @@
+"""Benchmark of the repartitioned pressure solve on one MI355X.
+
+Workload (default "c3"): a 256^3 7-point finite-volume system split over 64
+CPU ranks (4x4x4 blocks of 64^3 cells, log-uniform face coefficients in
+[1e-3, 1]), all 64 ranks fused onto this GPU.  Inputs are seeded and
+synthetic (no dataset); every timestep's per-rank coefficients are made on
+the host and put in HBM before the timed region.
+
+One step = one timestep of the whole path:
+  update     per-rank diag/upper/interface values (device memory) staged into
+             the receive buffer and reordered by P (FP64 + FP32 + Jacobi)
+  FP64 PCG   A x = b from x = 0 to ||b - A x|| <= 1e-8 ||b||
+  mixed      FP32 inner PCG under FP64 refinement, same b, x = 0, same target
+  adjoint    lambda = A^-1 (x - x_t) (FP64 PCG) and the slot gradient
+The plan (pattern, U, P) is built once before the steps and timed apart.
+
+Prints one JSON line.  value = median ms per FP64 pressure solve; the mixed
+solve, the SpMV bandwidth (HIP events around every FP64 SpMV launch inside
+the timed solves), the roofline of that kernel and the oracle timed on the
+host are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+METRIC = "ms per pressure solve to rel.res 1e-8 + SpMV HBM GB/s, FP64 vs mixed, 1 GPU"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=12,
+                    help="oracle PCG iterations timed for the CPU baseline sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 2 GiB device copy (reference for HBM byte counters)")
+    return ap.parse_args()
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
+              "the multi-GPU split is a design note, not part of it", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2510_08536_amd import Plan, default_opts, RP_KERNEL_SPMV64, RP_KERNEL_SPMV32, RP_KERNEL_SCATTER
+
+    assert torch.cuda.is_available()
+    dev = torch.device("cuda:0")
+    n_steps_total = a.warmup + a.steps
+    t0 = time.time()
+    w = synth.build(a.config, timesteps=max(n_steps_total, 1))
+    gen_s = time.time() - t0
+    p = w.part
+    ranks = [p.rank(r) for r in range(w.n_ranks)]
+    print(f"[bench] {a.config}: {w.n_cells} cells, {w.n_ranks} ranks, generated in {gen_s:.1f}s", flush=True)
+
+    # ---- plan (once) -------------------------------------------------------
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = Plan(p.n_cells, 0, w.n_ranks, ranks)
+    torch.cuda.synchronize()
+    plan_ms = 1e3 * (time.perf_counter() - t0)
+    n, nnz = plan.n_rows, plan.nnz
+    print(f"[bench] plan: n={n} nnz={nnz} slots={plan.n_slots} in {plan_ms:.1f} ms", flush=True)
+
+    # ---- per-timestep inputs, resident in HBM before timing ------------------
+    def to_dev(v):
+        return torch.from_numpy(np.ascontiguousarray(v)).to(dev)
+
+    steps_vals = []
+    for t in range(n_steps_total):
+        v = w.values(t)
+        steps_vals.append(([to_dev(v.diag[p.cell_ptr[r]:p.cell_ptr[r + 1]]) for r in range(w.n_ranks)],
+                           [to_dev(v.upper[p.face_ptr[r]:p.face_ptr[r + 1]]) for r in range(w.n_ranks)],
+                           [to_dev(v.iface[p.if_ptr[r]:p.if_ptr[r + 1]]) for r in range(w.n_ranks)]))
+    b = to_dev(w.rhs())
+    xt = to_dev(w.target())
+    print(f"[bench] {n_steps_total} timesteps of values resident in HBM", flush=True)
+
+    # PCIe-inclusive update from pinned host buffers (reported apart, never `value`)
+    vh = w.values(0)
+    pin = lambda a_: torch.from_numpy(np.ascontiguousarray(a_)).pin_memory()
+    host_vals = ([pin(vh.diag[p.cell_ptr[r]:p.cell_ptr[r + 1]]) for r in range(w.n_ranks)],
+                 [pin(vh.upper[p.face_ptr[r]:p.face_ptr[r + 1]]) for r in range(w.n_ranks)],
+                 [pin(vh.iface[p.if_ptr[r]:p.if_ptr[r + 1]]) for r in range(w.n_ranks)])
+    plan.update(*host_vals)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.update(*host_vals)
+    plan.sync()
+    update_host_ms = 1e3 * (time.perf_counter() - t0)
+    del host_vals
+
+    if a.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    o64 = lambda: default_opts(tol=1e-8, precision="fp64", x0_zero=1)
+    omx = lambda: default_opts(tol=1e-8, precision="mixed", x0_zero=1)
+    stream = torch.cuda.current_stream()
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    def one_step(t, rec):
+        d, u, i = steps_vals[t]
+        e0 = ev()
+        plan.update(d, u, i)
+        e1 = ev()
+        x64, inf64 = plan.solve(b, opts=o64())
+        e2 = ev()
+        xmx, infmx = plan.solve(b, opts=omx())
+        e3 = ev()
+        lam, infl = plan.solve(x64 - xt, opts=o64())
+        g = plan.value_grad(lam, x64)
+        e4 = ev()
+        if rec is not None:
+            rec.append(dict(ev=(e0, e1, e2, e3, e4), fp64=inf64, mixed=infmx, adj=infl,
+                            x64=x64, xmx=xmx))
+        for info in (inf64, infmx, infl):
+            assert info["status"] == 0 and info["rel_res"] <= 1e-8, info
+        return g
+
+    for t in range(a.warmup):
+        one_step(t, None)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({a.warmup} steps)", flush=True)
+
+    plan.set_timing(True)
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        one_step(a.warmup + k, recs)
+        print(f"[bench] step {k + 1}/{a.steps}: fp64 {recs[-1]['fp64']['iters']} it, "
+              f"mixed {recs[-1]['mixed']['iters']} inner/{recs[-1]['mixed']['outer_iters']} outer", flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n_spmv, ms_spmv = plan.kernel_stats(RP_KERNEL_SPMV64)
+    n_spmv32, ms_spmv32 = plan.kernel_stats(RP_KERNEL_SPMV32)
+    n_scat, ms_scat = plan.kernel_stats(RP_KERNEL_SCATTER)
+    plan.set_timing(False)
+
+    el = lambda e_a, e_b: e_a.elapsed_time(e_b)
+    upd = [el(r["ev"][0], r["ev"][1]) for r in recs]
+    f64 = [el(r["ev"][1], r["ev"][2]) for r in recs]
+    mx = [el(r["ev"][2], r["ev"][3]) for r in recs]
+    adj = [el(r["ev"][3], r["ev"][4]) for r in recs]
+    it64 = [r["fp64"]["iters"] for r in recs]
+    itmx = [r["mixed"]["iters"] for r in recs]
+    last = recs[-1]
+    diff = (torch.linalg.vector_norm(last["x64"] - last["xmx"]) / torch.linalg.vector_norm(last["x64"])).item()
+
+    # algorithmic bytes per unit (each array read once, ideal reuse of x)
+    spmv64_bytes = 12 * nnz + 20 * n + 4
+    spmv32_bytes = 8 * nnz + 12 * n + 4
+    iter64_bytes = 12 * nnz + 108 * n
+    iter32_bytes = 8 * nnz + 56 * n
+    spmv_avg_ms = ms_spmv / max(n_spmv, 1)
+    spmv_gbs = spmv64_bytes / (spmv_avg_ms * 1e-3) / 1e9
+    spmv32_gbs = spmv32_bytes / (ms_spmv32 / max(n_spmv32, 1) * 1e-3) / 1e9
+    med = lambda v: float(np.median(v))
+
+    out = {
+        "metric": METRIC,
+        "value": round(med(f64), 3),
+        "unit": "ms/solve",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(1e3 * wall / a.steps, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{a.config}: {w.recipe.note}", "n_rows": n, "nnz": nnz, "alpha": w.n_ranks,
+                   "tol": 1e-8, "x0": "zero",
+                   "step": "update + FP64 PCG + mixed PCG + adjoint (lambda solve + slot gradient)"},
+        "fp64": {"ms_per_solve": round(med(f64), 3), "iters": int(np.median(it64)),
+                 "ms_per_iter": round(med(f64) / max(np.median(it64), 1), 4),
+                 "iter_GBps_alg": round(iter64_bytes * np.median(it64) / (med(f64) * 1e-3) / 1e9, 1)},
+        "mixed": {"ms_per_solve": round(med(mx), 3), "inner_iters": int(np.median(itmx)),
+                  "outer_iters": int(last["mixed"]["outer_iters"]),
+                  "speedup_vs_fp64": round(med(f64) / med(mx), 3),
+                  "rel_diff_vs_fp64_solution": diff,
+                  "inner_iter_GBps_alg": round(iter32_bytes * np.median(itmx) / (med(mx) * 1e-3) / 1e9, 1)},
+        "adjoint_ms": round(med(adj), 3),
+        "update_ms": round(med(upd), 3),
+        "update_scatter_ms": round(ms_scat / max(n_scat, 1), 4),
+        "update_host_staged_ms": round(update_host_ms, 3),
+        "plan_ms": round(plan_ms, 1),
+        "spmv_GBps": round(spmv_gbs, 1),
+        "spmv32_GBps": round(spmv32_gbs, 1),
+        "roofline": {"bound": "hbm", "kernel": "cg_spmv_pq<double> (FP64 CSR SpMV + p.q)",
+                     "achieved": round(spmv_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(spmv_gbs / HBM_PEAK_GBS, 4),
+                     "bytes_per_launch": spmv64_bytes, "avg_launch_ms": round(spmv_avg_ms, 5),
+                     "launches": n_spmv, "traffic": None},
+    }
+
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_iters, med(f64), int(np.median(it64)),
+                                           n_steps_total - 1, last["x64"].cpu().numpy())
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+def cpu_baseline(w, iters, gpu_ms, gpu_iters, t_last, x_gpu):
+    """The oracle (serial C, one thread) on the same system: merge and update
+    timed in full, PCG timed over `iters` iterations and scaled to the GPU
+    solve's iteration count.  Also judges the last timed FP64 GPU solution
+    with the oracle's own residual."""
+    import oracle
+    ranks = [w.part.rank(r) for r in range(w.n_ranks)]
+    t0 = time.perf_counter()
+    m = oracle.merge(w.part.n_cells, 0, w.n_ranks, ranks)
+    merge_s = time.perf_counter() - t0
+    vals = w.values(t_last)
+    buf = oracle.receive_buffer([vals.rank(w.part, r) for r in range(w.n_ranks)])
+    t0 = time.perf_counter()
+    val64, *_ = oracle.update(m, buf)
+    update_s = time.perf_counter() - t0
+    b = w.rhs()
+    t0 = time.perf_counter()
+    _, st, it, _, _ = oracle.pcg(m, val64, b, tol=1e-8, max_iter=iters)
+    pcg_s = time.perf_counter() - t0
+    per_iter_ms = 1e3 * pcg_s / max(it, 1)
+    est_ms = per_iter_ms * gpu_iters
+    rr_gpu = oracle.true_relres(m, val64, b, x_gpu)
+    return {"value": round(est_ms, 1), "unit": "ms/solve", "cores": 1, "kind": "oracle",
+            "sample": f"{it} serial FP64 PCG iterations on the same {w.n_cells}-row system "
+                      f"({per_iter_ms:.1f} ms/iteration), scaled to the GPU solve's {gpu_iters} iterations; "
+                      f"merge {merge_s:.1f} s and update {1e3 * update_s:.0f} ms timed in full",
+            "merge_s": round(merge_s, 2), "update_ms": round(1e3 * update_s, 1),
+            "pcg_ms_per_iter": round(per_iter_ms, 2), "gpu_speedup": round(est_ms / gpu_ms, 1),
+            "host_cpu": cpu_model(), "host_nproc": os.cpu_count(),
+            "oracle_rel_res_of_gpu_fp64_x": rr_gpu}
+
+
+if __name__ == "__main__":
+    main()
