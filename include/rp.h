@@ -63,8 +63,9 @@ extern "C" {
 
 /* ---- precisions -------------------------------------------------------- */
 #define RP_FP64 0                 /* FP64 everywhere */
-#define RP_MIXED 1                /* FP32 inner PCG, FP64 refinement (solve only) */
+#define RP_MIXED 1                /* FP32 PCG with FP64 residual-replacement updates (solve only) */
 #define RP_FP32 2                 /* FP32 matrix and vectors (rp_spmv only) */
+#define RP_MIXED_IR 3             /* FP32 inner PCG restarted under FP64 refinement (solve only) */
 
 typedef struct rp_plan rp_plan;
 
@@ -84,10 +85,12 @@ typedef struct rp_rank_desc {
 
 typedef struct rp_solve_opts {
     double tol;              /* stop when ||b - A x||_2 <= tol ||b||_2 (default 1e-8) */
-    double inner_tol;        /* RP_MIXED: inner FP32 relative tolerance (default 1e-4) */
-    int32_t max_iter;        /* FP64: CG iterations; RP_MIXED: total inner iterations */
-    int32_t precision;       /* RP_FP64 or RP_MIXED */
-    int32_t max_outer;       /* RP_MIXED: refinement steps (default 50) */
+    double inner_tol;        /* RP_MIXED_IR: inner FP32 relative tolerance (default 1e-4) */
+    double update_delta;     /* RP_MIXED: the FP64 update is due once the FP32 residual has
+                                fallen by this factor since the last one (default 0.1) */
+    int32_t max_iter;        /* FP64: CG iterations; mixed: total FP32 iterations */
+    int32_t precision;       /* RP_FP64, RP_MIXED or RP_MIXED_IR */
+    int32_t max_outer;       /* mixed: FP64 residual updates / refinement steps (default 200) */
     int32_t check_every;     /* host reads the device convergence state every this
                                 many iterations (default 32); iteration counts do
                                 not depend on it */
@@ -98,8 +101,8 @@ typedef struct rp_solve_opts {
 
 typedef struct rp_solve_info {
     int32_t status;          /* the returned status */
-    int32_t iters;           /* FP64 CG iterations, or total inner FP32 iterations */
-    int32_t outer_iters;     /* RP_MIXED refinement steps (0 for RP_FP64) */
+    int32_t iters;           /* FP64 CG iterations, or total FP32 iterations */
+    int32_t outer_iters;     /* mixed: FP64 residual updates (0 for RP_FP64) */
     int32_t restarts;        /* true-residual restarts */
     double rel_res;          /* ||b - A x||_2 / ||b||_2 at exit, FP64 on the GPU */
 } rp_solve_info;
@@ -163,6 +166,12 @@ int rp_update_values_slots(rp_plan* plan, const double* slots, void* stream);
 int rp_spmv(rp_plan* plan, int32_t precision, const void* x, void* y, void* stream);
 
 /* ---- solve (Sec. 4: CG for the pressure system) ------------------------ *
+ * RP_FP64 is Jacobi-PCG in FP64.  RP_MIXED runs the same PCG in FP32 (FP32
+ * matrix, preconditioner, vectors and dot products) and, whenever its
+ * residual has fallen by update_delta, folds its correction into the FP64
+ * solution and replaces its residual by the FP64 residual b - A x, keeping
+ * the search direction; the stop test is on that FP64 residual.  RP_MIXED_IR
+ * restarts an FP32 PCG (to inner_tol) on every FP64 refinement residual.
  * b, x: device arrays of n_rows doubles in fused row order (the share's
  * ranks in order, each in local cell order).  x holds x0 on entry (unless
  * opts->x0_zero) and the solution on return.  opts NULL = defaults.  Blocks

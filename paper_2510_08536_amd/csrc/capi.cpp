@@ -80,6 +80,7 @@ void free_plan(rp_plan* p) {
         if (q) (void)hipFree(q);
     if (p->h_st64) (void)hipHostFree(p->h_st64);
     if (p->h_st32) (void)hipHostFree(p->h_st32);
+    if (p->h_st_outer) (void)hipHostFree(p->h_st_outer);
     if (p->h_flags) (void)hipHostFree(p->h_flags);
     for (auto& e : p->timing.pool) {
         for (hipEvent_t ev : e.start) (void)hipEventDestroy(ev);
@@ -108,7 +109,7 @@ int alloc_values(rp_plan* p) {
     RP_TRY(dalloc(&p->d_p32, n));
     RP_TRY(dalloc(&p->d_q32, n));
     RP_TRY(dalloc(&p->d_x32, n));
-    RP_HIP_TRY(hipMalloc(&p->d_partials, sizeof(double) * 2 * MAX_PARTIALS));
+    RP_HIP_TRY(hipMalloc(&p->d_partials, sizeof(double) * PART_TOTAL));
     RP_TRY(dalloc(&p->d_st64, 1));
     RP_TRY(dalloc(&p->d_st32, 1));
     RP_TRY(dalloc(&p->d_st_outer, 1));
@@ -117,6 +118,7 @@ int alloc_values(rp_plan* p) {
     RP_HIP_TRY(hipMemset(p->d_st_outer, 0, sizeof(CgState<double>)));
     RP_HIP_TRY(hipHostMalloc((void**)&p->h_st64, sizeof(CgState<double>), hipHostMallocDefault));
     RP_HIP_TRY(hipHostMalloc((void**)&p->h_st32, sizeof(CgState<float>), hipHostMallocDefault));
+    RP_HIP_TRY(hipHostMalloc((void**)&p->h_st_outer, sizeof(CgState<double>), hipHostMallocDefault));
     RP_HIP_TRY(hipHostMalloc((void**)&p->h_flags, 2 * sizeof(uint32_t), hipHostMallocDefault));
     return RP_OK;
 }
@@ -345,9 +347,10 @@ void rp_solve_opts_default(rp_solve_opts* o) {
     if (!o) return;
     o->tol = 1e-8;
     o->inner_tol = 1e-4;
+    o->update_delta = 0.1;
     o->max_iter = 100000;
     o->precision = RP_FP64;
-    o->max_outer = 50;
+    o->max_outer = 200;
     o->check_every = 32;
     o->x0_zero = 0;
     o->max_restarts = 5;
@@ -365,11 +368,11 @@ int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, 
     rp_solve_opts_default(&o);
     if (opts) o = *opts;
     RP_CHECK(p->n_rows == 0 || (b && x), RP_ERR_ARG, "b or x is NULL");
-    RP_CHECK(o.tol >= 0.0 && o.inner_tol > 0.0 && o.inner_tol < 1.0 && o.max_iter >= 0 && o.max_outer >= 0 &&
-                 o.max_restarts >= 0,
+    RP_CHECK(o.tol >= 0.0 && o.inner_tol > 0.0 && o.inner_tol < 1.0 && o.update_delta > 0.0 &&
+                 o.update_delta < 1.0 && o.max_iter >= 0 && o.max_outer >= 0 && o.max_restarts >= 0,
              RP_ERR_ARG, "bad solve options");
-    RP_CHECK(o.precision == RP_FP64 || o.precision == RP_MIXED, RP_ERR_ARG,
-             "precision must be RP_FP64 or RP_MIXED");
+    RP_CHECK(o.precision == RP_FP64 || o.precision == RP_MIXED || o.precision == RP_MIXED_IR, RP_ERR_ARG,
+             "precision must be RP_FP64, RP_MIXED or RP_MIXED_IR");
     RP_TRY(activate(p));
     hipStream_t s = as_stream(stream);
     p->last_stream = s;
@@ -379,7 +382,7 @@ int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, 
     } else if (o.precision == RP_FP64) {
         rc = solve_fp64(p, b, x, o, inf, s);
     } else {
-        rc = solve_mixed(p, b, x, o, inf, s);
+        rc = solve_mixed(p, b, x, o, inf, s, o.precision == RP_MIXED);
     }
     inf.status = rc;
     return rc;

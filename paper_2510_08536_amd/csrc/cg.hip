@@ -1,19 +1,23 @@
 // Jacobi-preconditioned CG (the CG pressure solve of Sec. 4, M = diag(A)) and
-// the FP32-inner / FP64-outer iterative refinement built on it.
+// the two mixed-precision forms built on it.
 //
-// One iteration is three kernels; all scalars stay on the device:
-//   K1  q = A p, pq = (p, q)                   -> alpha = rz / pq
-//   K2  x += alpha p, r -= alpha q, z = M^-1 r,
-//       rz' = (r, z), rr = (r, r)              -> stop test, beta = rz'/rz
-//   K3  p = M^-1 r + beta p
-// Each reduction ends in the block that arrives last, which sums the
-// per-block partials in index order (deterministic, no floating-point
-// atomics) and updates the state.  Once the state says "done", every later
-// kernel returns at entry, so the host can enqueue iterations in chunks and
-// read the state only between chunks; the iteration count does not depend on
-// the chunk length.  The stop test is ||r||^2 <= tol^2 ||b||^2 on the
-// recurrence residual, then confirmed on b - A x; a failed confirmation
-// restarts CG from the current x.
+// Iteration k is three kernels; all scalars stay on the device:
+//   K1  q = A p                      partials of (p, q)
+//   K2  alpha = rz_k / (p, q)        x += alpha p, r -= alpha q;
+//                                    partials of (r, M^-1 r) and (r, r)
+//   K3  stop tests, beta = rz_{k+1} / rz_k, p = M^-1 r + beta p
+// Each kernel starts by adding up the previous kernel's per-block partials
+// (every block the same sum, in index order), so reductions need no atomics,
+// no fences and no extra launches, and reruns are bit-identical.  The
+// iteration number k is a kernel argument; rz is kept in a ring indexed by
+// it, because block 0 of K3 stores rz_{k+1} while other blocks still read
+// rz_k.  Block 0 also records the state the host reads between chunks of
+// iterations.  A stop decision is taken identically by every block, and
+// kernels enqueued after a stop return at entry, so the iteration count does
+// not depend on how many iterations the host enqueues per chunk.
+//
+// Stop test: ||r||^2 <= tol^2 ||b||^2 on the recurrence residual, then
+// confirmed on b - A x; a failed confirmation restarts CG from the current x.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -28,20 +32,19 @@ namespace {
 // kernels
 // ---------------------------------------------------------------------------
 
-// r = b - A x (x = 0 when XZERO, and then x is cleared), partial sums of
-// (r, r) and (b, b); with W32 also r32 = RNE(r).  Last block stores rr_true
-// and bb.
+// r = b - A x (x = 0 when XZERO, and then x is cleared); with W32 also
+// r32 = RNE(r).  Partials of (r, r) -> PART_A and (b, b) -> PART_B.
 template <typename T, bool XZERO, bool W32>
 __global__ void __launch_bounds__(SPMV_BLOCK)
 residual_kernel(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                 const T* __restrict__ val, T* __restrict__ x, const T* b, T* r, float* r32,
-                T* __restrict__ part, CgState<T>* st) {
+                T* __restrict__ part) {
 #pragma clang fp contract(off)
     __shared__ T lds[XZERO ? 1 : SPMV_CAP];
     __shared__ T red[SPMV_BLOCK / 64];
     T prr = T(0), pbb = T(0);
     const GroupRange gr = block_groups(n);
-    for (int32_t g = gr.g0; g < gr.g1; ++g) {
+    for (int32_t g = gr.g0; g < gr.n_groups; g += gr.step) {
         const int32_t r0 = g * SPMV_BLOCK;
         const int32_t nr = min(SPMV_BLOCK, n - r0);
         T s = T(0);
@@ -59,27 +62,18 @@ residual_kernel(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* _
     }
     const T brr = block_sum<T, SPMV_BLOCK>(prr, red);
     const T bbb = block_sum<T, SPMV_BLOCK>(pbb, red);
-    const int32_t L = xcd_block();
     if (threadIdx.x == 0) {
-        store_partial(part + L, brr);
-        store_partial(part + MAX_PARTIALS + L, bbb);
-    }
-    if (arrive_last(&st->counter[0], gridDim.x)) {
-        const T rr = sum_partials<T, SPMV_BLOCK>(part, gridDim.x, red);
-        const T bb = sum_partials<T, SPMV_BLOCK>(part + MAX_PARTIALS, gridDim.x, red);
-        if (threadIdx.x == 0) {
-            st->rr_true = rr;
-            st->bb = bb;
-            st->counter[0] = 0;
-        }
+        const int32_t L = xcd_block();
+        part[PART_A + L] = brr;
+        part[PART_B + L] = bbb;
     }
 }
 
-// start (or restart) CG from the residual in r: p = M^-1 r, rz = (r, p)
+// p = M^-1 r; partials of (r, M^-1 r) -> PART_RZ
 template <typename T>
 __global__ void __launch_bounds__(VEC_BLOCK)
-cg_start(int32_t n, const T* __restrict__ r, const T* __restrict__ dinv, T* __restrict__ p, T tol2,
-         T* __restrict__ part, CgState<T>* st) {
+cg_start_p(int32_t n, const T* __restrict__ r, const T* __restrict__ dinv, T* __restrict__ p,
+           T* __restrict__ part) {
 #pragma clang fp contract(off)
     __shared__ T red[VEC_BLOCK / 64];
     T prz = T(0);
@@ -89,39 +83,77 @@ cg_start(int32_t n, const T* __restrict__ r, const T* __restrict__ dinv, T* __re
         p[i] = zi;
         prz += ri * zi;
     }
-    const T brz = block_sum<T, VEC_BLOCK>(prz, red);
-    if (threadIdx.x == 0) store_partial(part + blockIdx.x, brz);
-    if (arrive_last(&st->counter[0], gridDim.x)) {
-        const T rz = sum_partials<T, VEC_BLOCK>(part, gridDim.x, red);
-        if (threadIdx.x == 0) {
-            const T thresh = tol2 * st->bb;
-            st->rz = rz;
-            st->rr = st->rr_true;
-            st->thresh = thresh;
-            int32_t d = CG_RUNNING;
-            if (st->bb == T(0)) d = CG_ZERO_RHS;
-            else if (st->rr_true <= thresh) d = CG_CONVERGED;
-            else if (!(rz > T(0)) || !isfinite(rz)) d = CG_BREAKDOWN;
-            else if (st->iter >= st->max_iter) d = CG_MAX_ITER;
-            st->done = d;
-            st->counter[0] = 0;
-        }
+    const T b = block_sum<T, VEC_BLOCK>(prz, red);
+    if (threadIdx.x == 0) part[PART_RZ + blockIdx.x] = b;
+}
+
+// partials of (r, M^-1 r) -> PART_RZ and (r, r) -> PART_RR for a replaced residual
+template <typename T>
+__global__ void __launch_bounds__(VEC_BLOCK)
+cg_rz_rr(int32_t n, const T* __restrict__ r, const T* __restrict__ dinv, T* __restrict__ part) {
+#pragma clang fp contract(off)
+    __shared__ T red[VEC_BLOCK / 64];
+    T prz = T(0), prr = T(0);
+    for (int32_t i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK) {
+        const T ri = r[i];
+        prz += ri * (dinv[i] * ri);
+        prr += ri * ri;
+    }
+    const T b1 = block_sum<T, VEC_BLOCK>(prz, red);
+    const T b2 = block_sum<T, VEC_BLOCK>(prr, red);
+    if (threadIdx.x == 0) {
+        part[PART_RZ + blockIdx.x] = b1;
+        part[PART_RR + blockIdx.x] = b2;
     }
 }
 
-// K1: q = A p, pq = (p, q), alpha = rz / pq
+enum : int32_t { FIN_START = 0, FIN_RESIDUAL = 1 };
+
+// one block.  FIN_RESIDUAL: rr_true, bb from a residual_kernel.
+// FIN_START: additionally (re)start CG at iteration k from that residual and
+// cg_start_p's (r, z): thresh = tol2 * bb, pause_thresh = pause_frac2 * rr.
+template <typename T>
+__global__ void __launch_bounds__(VEC_BLOCK)
+cg_finalize(int32_t mode, int32_t k, T tol2, T pause_frac2, int32_t g_spmv, int32_t g_vec,
+            const T* __restrict__ part, CgState<T>* st) {
+#pragma clang fp contract(off)
+    __shared__ T red[VEC_BLOCK / 64];
+    const T rr = sum_partials_all<T, VEC_BLOCK>(part + PART_A, g_spmv, red);
+    const T bb = sum_partials_all<T, VEC_BLOCK>(part + PART_B, g_spmv, red);
+    T rz = T(0);
+    if (mode == FIN_START) rz = sum_partials_all<T, VEC_BLOCK>(part + PART_RZ, g_vec, red);
+    if (threadIdx.x != 0) return;
+    st->rr_true = rr;
+    st->bb = bb;
+    if (mode != FIN_START) return;
+    const T thresh = tol2 * bb;
+    st->thresh = thresh;
+    st->rz[k & 3] = rz;
+    st->rr = rr;
+    st->rr_ref = rr;
+    st->pause_frac2 = pause_frac2;
+    st->pause_thresh = pause_frac2 * rr;
+    st->iter = k;
+    int32_t d = CG_RUNNING;
+    if (bb == T(0)) d = CG_ZERO_RHS;
+    else if (rr <= thresh) d = CG_CONVERGED;
+    else if (!(rz > T(0)) || !isfinite(rz)) d = CG_BREAKDOWN;
+    st->done = d;
+}
+
+// K1: q = A p; partials of (p, q) -> PART_A
 template <typename T>
 __global__ void __launch_bounds__(SPMV_BLOCK)
 cg_spmv_pq(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
            const T* __restrict__ val, const T* __restrict__ p, T* __restrict__ q, T* __restrict__ part,
-           CgState<T>* st) {
+           const CgState<T>* st) {
 #pragma clang fp contract(off)
     if (st->done != CG_RUNNING) return;
     __shared__ T lds[SPMV_CAP];
     __shared__ T red[SPMV_BLOCK / 64];
     T ppq = T(0);
     const GroupRange gr = block_groups(n);
-    for (int32_t g = gr.g0; g < gr.g1; ++g) {
+    for (int32_t g = gr.g0; g < gr.n_groups; g += gr.step) {
         const int32_t r0 = g * SPMV_BLOCK;
         const int32_t nr = min(SPMV_BLOCK, n - r0);
         const T s = spmv_group_row(row_ptr, col, val, p, r0, nr, lds);
@@ -131,28 +163,30 @@ cg_spmv_pq(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __rest
             ppq += p[i] * s;
         }
     }
-    const T bpq = block_sum<T, SPMV_BLOCK>(ppq, red);
-    if (threadIdx.x == 0) store_partial(part + xcd_block(), bpq);
-    if (arrive_last(&st->counter[0], gridDim.x)) {
-        const T pq = sum_partials<T, SPMV_BLOCK>(part, gridDim.x, red);
-        if (threadIdx.x == 0) {
-            st->pq = pq;
-            if (!(pq > T(0)) || !isfinite(pq)) st->done = CG_BREAKDOWN;
-            else st->alpha = st->rz / pq;
-            st->counter[0] = 0;
-        }
-    }
+    const T b = block_sum<T, SPMV_BLOCK>(ppq, red);
+    if (threadIdx.x == 0) part[PART_A + xcd_block()] = b;
 }
 
-// K2: x += alpha p, r -= alpha q, rz' = (r, M^-1 r), rr = (r, r); stop test, beta
+// K2: alpha = rz_k / (p, q); x += alpha p, r -= alpha q; partials of
+// (r, M^-1 r) -> PART_RZ and (r, r) -> PART_RR
 template <typename T>
 __global__ void __launch_bounds__(VEC_BLOCK)
-cg_update_xr(int32_t n, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-             const T* __restrict__ q, const T* __restrict__ dinv, T* __restrict__ part, CgState<T>* st) {
+cg_update_xr(int32_t n, int32_t k, int32_t g_spmv, T* __restrict__ x, T* __restrict__ r,
+             const T* __restrict__ p, const T* __restrict__ q, const T* __restrict__ dinv,
+             T* __restrict__ part, CgState<T>* st) {
 #pragma clang fp contract(off)
     if (st->done != CG_RUNNING) return;
     __shared__ T red[VEC_BLOCK / 64];
-    const T a = st->alpha;
+    const T pq = sum_partials_all<T, VEC_BLOCK>(part + PART_A, g_spmv, red);
+    if (!(pq > T(0)) || !isfinite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->pq = pq;
+            st->iter = k;
+            st->done = CG_BREAKDOWN;
+        }
+        return;
+    }
+    const T a = st->rz[k & 3] / pq;
     T prz = T(0), prr = T(0);
     for (int32_t i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK) {
         const T xi = x[i] + a * p[i];
@@ -163,49 +197,67 @@ cg_update_xr(int32_t n, T* __restrict__ x, T* __restrict__ r, const T* __restric
         prz += ri * zi;
         prr += ri * ri;
     }
-    const T brz = block_sum<T, VEC_BLOCK>(prz, red);
-    const T brr = block_sum<T, VEC_BLOCK>(prr, red);
+    const T b1 = block_sum<T, VEC_BLOCK>(prz, red);
+    const T b2 = block_sum<T, VEC_BLOCK>(prr, red);
     if (threadIdx.x == 0) {
-        store_partial(part + blockIdx.x, brz);
-        store_partial(part + MAX_PARTIALS + blockIdx.x, brr);
-    }
-    if (arrive_last(&st->counter[1], gridDim.x)) {
-        const T rz = sum_partials<T, VEC_BLOCK>(part, gridDim.x, red);
-        const T rr = sum_partials<T, VEC_BLOCK>(part + MAX_PARTIALS, gridDim.x, red);
-        if (threadIdx.x == 0) {
-            const int32_t it = st->iter + 1;
-            st->iter = it;
-            st->rr = rr;
-            if (rr <= st->thresh) st->done = CG_CONVERGED;
-            else if (!(rz > T(0)) || !isfinite(rz)) st->done = CG_BREAKDOWN;
-            else if (it >= st->max_iter) st->done = CG_MAX_ITER;
-            else {
-                st->beta = rz / st->rz;
-                st->rz = rz;
-            }
-            st->counter[1] = 0;
+        part[PART_RZ + blockIdx.x] = b1;
+        part[PART_RR + blockIdx.x] = b2;
+        if (blockIdx.x == 0) {
+            st->pq = pq;
+            st->alpha = a;
         }
     }
 }
 
-// K3: p = M^-1 r + beta p
+// K3: stop tests on (r, r), beta = rz_{k+1} / rz_k, p = M^-1 r + beta p.
+// resume: continue after the residual was replaced (partials from cg_rz_rr),
+// skipping the stop tests.
 template <typename T>
 __global__ void __launch_bounds__(VEC_BLOCK)
-cg_update_p(int32_t n, const T* __restrict__ r, const T* __restrict__ dinv, T* __restrict__ p,
-            const CgState<T>* st) {
+cg_update_p(int32_t n, int32_t k, int32_t g_vec, int32_t resume, const T* __restrict__ r,
+            const T* __restrict__ dinv, T* __restrict__ p, const T* __restrict__ part, CgState<T>* st) {
 #pragma clang fp contract(off)
-    if (st->done != CG_RUNNING) return;
-    const T beta = st->beta;
+    if (!resume && st->done != CG_RUNNING) return;
+    __shared__ T red[VEC_BLOCK / 64];
+    const T rz = sum_partials_all<T, VEC_BLOCK>(part + PART_RZ, g_vec, red);
+    const T rr = sum_partials_all<T, VEC_BLOCK>(part + PART_RR, g_vec, red);
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    int32_t stop = CG_RUNNING;
+    if (!resume && rr <= st->thresh) stop = CG_CONVERGED;
+    else if (!(rz > T(0)) || !isfinite(rz)) stop = CG_BREAKDOWN;
+    else if (!resume && rr <= st->pause_thresh) stop = CG_PAUSED;
+    if (stop != CG_RUNNING) {
+        if (lead) {
+            st->rr = rr;
+            st->iter = k + 1;
+            st->done = stop;
+        }
+        return;
+    }
+    const T beta = rz / st->rz[k & 3];
     for (int32_t i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK)
         p[i] = dinv[i] * r[i] + beta * p[i];
+    if (lead) {
+        st->rz[(k + 1) & 3] = rz;
+        st->rr = rr;
+        st->beta = beta;
+        st->iter = k + 1;
+        if (resume) {
+            st->rr_ref = rr;
+            st->pause_thresh = st->pause_frac2 * rr;
+            st->done = CG_RUNNING;
+        }
+    }
 }
 
-// refinement: x += (double) d
+// x64 += (double) x32, then x32 = 0
 __global__ void __launch_bounds__(VEC_BLOCK)
-ir_accumulate(int32_t n, double* __restrict__ x, const float* __restrict__ d) {
+ir_accumulate(int32_t n, double* __restrict__ x, float* __restrict__ d) {
 #pragma clang fp contract(off)
-    for (int32_t i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK)
+    for (int32_t i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK) {
         x[i] = x[i] + (double)d[i];
+        d[i] = 0.0f;
+    }
 }
 
 __global__ void fill_zero(int32_t n, double* x) {
@@ -233,7 +285,16 @@ struct Cg {
     CgState<T>* h;      // pinned host mirror
     int kernel_id;      // RP_KERNEL_SPMV64 / RP_KERNEL_SPMV32
     hipStream_t s;
+    int32_t g_spmv, g_vec;
 };
+
+template <typename T>
+Cg<T> make_cg(rp_plan* p, const T* val, const T* dinv, T* x, const T* b, T* r, T* pv, T* q, CgState<T>* st,
+              CgState<T>* h, int kernel_id, hipStream_t s) {
+    Cg<T> c{p, (int32_t)p->n_rows, p->d_row_ptr, p->d_col, val, dinv, x, b, r, pv, q, (T*)p->d_partials, st, h,
+            kernel_id, s, spmv_grid(p->n_rows), vec_grid(p->n_rows)};
+    return c;
+}
 
 template <typename T>
 int read_state(Cg<T>& c) {
@@ -242,57 +303,66 @@ int read_state(Cg<T>& c) {
     return RP_OK;
 }
 
-template <typename T>
-int init_state(Cg<T>& c, int32_t max_iter) {
-    CgState<T> z;
-    std::memset(&z, 0, sizeof(z));
-    z.max_iter = max_iter;
-    z.done = CG_RUNNING;
-    // the pinned mirror is the copy source; make sure an earlier read is done
-    RP_HIP_TRY(hipStreamSynchronize(c.s));
-    *c.h = z;
-    RP_HIP_TRY(hipMemcpyAsync(c.st, c.h, sizeof(CgState<T>), hipMemcpyHostToDevice, c.s));
-    return RP_OK;
-}
-
 template <typename T, bool W32>
 int launch_residual(Cg<T>& c, bool xzero, float* r32) {
-    const dim3 g(spmv_grid(c.n)), bl(SPMV_BLOCK);
+    const dim3 g(c.g_spmv), bl(SPMV_BLOCK);
     if (xzero)
         hipLaunchKernelGGL((residual_kernel<T, true, W32>), g, bl, 0, c.s, c.n, c.row_ptr, c.col, c.val, c.x,
-                           c.b, c.r, r32, c.part, c.st);
+                           c.b, c.r, r32, c.part);
     else
         hipLaunchKernelGGL((residual_kernel<T, false, W32>), g, bl, 0, c.s, c.n, c.row_ptr, c.col, c.val, c.x,
-                           c.b, c.r, r32, c.part, c.st);
+                           c.b, c.r, r32, c.part);
     RP_HIP_TRY(hipGetLastError());
     return RP_OK;
 }
 
 template <typename T>
-int launch_start(Cg<T>& c, T tol2) {
-    hipLaunchKernelGGL(cg_start<T>, dim3(vec_grid(c.n)), dim3(VEC_BLOCK), 0, c.s, c.n, c.r, c.dinv, c.p, tol2,
-                       c.part, c.st);
+int launch_finalize(Cg<T>& c, int32_t mode, int32_t k, T tol2, T pause_frac2) {
+    hipLaunchKernelGGL(cg_finalize<T>, dim3(1), dim3(VEC_BLOCK), 0, c.s, mode, k, tol2, pause_frac2, c.g_spmv,
+                       c.g_vec, c.part, c.st);
     RP_HIP_TRY(hipGetLastError());
     return RP_OK;
 }
 
-// enqueue chunks of `chunk` iterations until the state leaves CG_RUNNING
+// (re)start at iteration k from the residual in r (the residual_kernel's
+// partials are still in PART_A / PART_B)
 template <typename T>
-int iterate(Cg<T>& c, int chunk) {
-    const dim3 gs(spmv_grid(c.n)), bs(SPMV_BLOCK), gv(vec_grid(c.n)), bv(VEC_BLOCK);
-    while (c.h->done == CG_RUNNING) {
-        const int32_t it0 = c.h->iter;
-        for (int k = 0; k < chunk; ++k) {
+int launch_start(Cg<T>& c, int32_t k, T tol2, T pause_frac2) {
+    hipLaunchKernelGGL(cg_start_p<T>, dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, c.r, c.dinv, c.p, c.part);
+    RP_HIP_TRY(hipGetLastError());
+    return launch_finalize(c, FIN_START, k, tol2, pause_frac2);
+}
+
+// continue after r was replaced: beta from the new (r, z), p update, running again
+template <typename T>
+int launch_resume(Cg<T>& c) {
+    const int32_t k = c.h->iter - 1;
+    hipLaunchKernelGGL(cg_rz_rr<T>, dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, c.r, c.dinv, c.part);
+    hipLaunchKernelGGL(cg_update_p<T>, dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, k, c.g_vec, 1, c.r, c.dinv,
+                       c.p, c.part, c.st);
+    RP_HIP_TRY(hipGetLastError());
+    return RP_OK;
+}
+
+// enqueue chunks of up to `chunk` iterations (never past max_iter) until the
+// state leaves CG_RUNNING or the budget is spent
+template <typename T>
+int iterate(Cg<T>& c, int chunk, int32_t max_iter) {
+    const dim3 gs(c.g_spmv), bs(SPMV_BLOCK), gv(c.g_vec), bv(VEC_BLOCK);
+    while (c.h->done == CG_RUNNING && c.h->iter < max_iter) {
+        const int32_t k0 = c.h->iter;
+        const int32_t k1 = (int32_t)std::min<int64_t>((int64_t)k0 + chunk, max_iter);
+        for (int32_t k = k0; k < k1; ++k) {
             RP_TRY(timing_begin(c.plan, c.kernel_id, c.s));
-            hipLaunchKernelGGL(cg_spmv_pq<T>, gs, bs, 0, c.s, c.n, c.row_ptr, c.col, c.val, c.p, c.q, c.part,
-                               c.st);
+            hipLaunchKernelGGL(cg_spmv_pq<T>, gs, bs, 0, c.s, c.n, c.row_ptr, c.col, c.val, c.p, c.q, c.part, c.st);
             RP_TRY(timing_end(c.plan, c.kernel_id, c.s));
-            hipLaunchKernelGGL(cg_update_xr<T>, gv, bv, 0, c.s, c.n, c.x, c.r, c.p, c.q, c.dinv, c.part, c.st);
-            hipLaunchKernelGGL(cg_update_p<T>, gv, bv, 0, c.s, c.n, c.r, c.dinv, c.p, c.st);
+            hipLaunchKernelGGL(cg_update_xr<T>, gv, bv, 0, c.s, c.n, k, c.g_spmv, c.x, c.r, c.p, c.q, c.dinv,
+                               c.part, c.st);
+            hipLaunchKernelGGL(cg_update_p<T>, gv, bv, 0, c.s, c.n, k, c.g_vec, 0, c.r, c.dinv, c.p, c.part, c.st);
         }
         RP_HIP_TRY(hipGetLastError());
         RP_TRY(read_state(c));
-        RP_TRY(timing_collect(c.plan, c.kernel_id, (int64_t)c.h->iter - it0));
+        RP_TRY(timing_collect(c.plan, c.kernel_id, (int64_t)c.h->iter - k0));
     }
     return RP_OK;
 }
@@ -330,14 +400,12 @@ int check_solvable(rp_plan* p, hipStream_t s) {
 int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
                hipStream_t s) {
     RP_TRY(check_solvable(p, s));
-    Cg<double> c{p, (int32_t)p->n_rows, p->d_row_ptr, p->d_col, p->d_val64, p->d_dinv64, x, b,
-                 p->d_r, p->d_p, p->d_q, (double*)p->d_partials, p->d_st64, p->h_st64,
-                 RP_KERNEL_SPMV64, s};
+    Cg<double> c = make_cg<double>(p, p->d_val64, p->d_dinv64, x, b, p->d_r, p->d_p, p->d_q, p->d_st64,
+                                   p->h_st64, RP_KERNEL_SPMV64, s);
     const double tol2 = o.tol * o.tol;
     const int chunk = std::max(1, o.check_every);
-    RP_TRY(init_state(c, o.max_iter));
     RP_TRY((launch_residual<double, false>(c, o.x0_zero != 0, nullptr)));
-    RP_TRY(launch_start(c, tol2));
+    RP_TRY(launch_start(c, 0, tol2, 0.0));
     RP_TRY(read_state(c));
     bool fresh = true;  // rr_true belongs to the current x
     int status = RP_NOT_CONVERGED;
@@ -345,7 +413,7 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
     for (;;) {
         const int32_t d = c.h->done;
         if (d == CG_ZERO_RHS) {
-            hipLaunchKernelGGL(fill_zero, dim3(vec_grid(c.n)), dim3(VEC_BLOCK), 0, s, c.n, x);
+            hipLaunchKernelGGL(fill_zero, dim3(c.g_vec), dim3(VEC_BLOCK), 0, s, c.n, x);
             RP_HIP_TRY(hipGetLastError());
             status = RP_OK;
             break;
@@ -353,6 +421,7 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
         if (d == CG_CONVERGED) {
             if (!fresh) {
                 RP_TRY((launch_residual<double, false>(c, false, nullptr)));
+                RP_TRY(launch_finalize(c, FIN_RESIDUAL, 0, 0.0, 0.0));
                 RP_TRY(read_state(c));
                 fresh = true;
             }
@@ -362,7 +431,7 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
             }
             if (info.restarts >= o.max_restarts) break;
             ++info.restarts;
-            RP_TRY(launch_start(c, tol2));
+            RP_TRY(launch_start(c, c.h->iter, tol2, 0.0));
             RP_TRY(read_state(c));
             continue;
         }
@@ -371,12 +440,13 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
             set_error("CG breakdown after %d iterations (p.Ap = %g)", c.h->iter, c.h->pq);
             break;
         }
-        if (d == CG_MAX_ITER) break;
-        RP_TRY(iterate(c, chunk));
+        if (c.h->iter >= o.max_iter) break;
+        RP_TRY(iterate(c, chunk, o.max_iter));
         fresh = false;
     }
     if (!fresh && c.h->done != CG_ZERO_RHS) {
         RP_TRY((launch_residual<double, false>(c, false, nullptr)));
+        RP_TRY(launch_finalize(c, FIN_RESIDUAL, 0, 0.0, 0.0));
         RP_TRY(read_state(c));
     }
     info.iters = c.h->iter;
@@ -389,56 +459,77 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
 }
 
 int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
-                hipStream_t s) {
+                hipStream_t s, bool reliable) {
     RP_TRY(check_solvable(p, s));
-    const int32_t n = (int32_t)p->n_rows;
-    // outer FP64 residual: r64 = b - A x, r32 = RNE(r64)
-    Cg<double> out{p, n, p->d_row_ptr, p->d_col, p->d_val64, p->d_dinv64, x, b, p->d_r, p->d_p, p->d_q,
-                   (double*)p->d_partials, p->d_st_outer, p->h_st64, RP_KERNEL_SPMV64, s};
-    // inner FP32 PCG on A32 d = r32 from d = 0 (b and r alias r32)
-    Cg<float> in{p, n, p->d_row_ptr, p->d_col, p->d_val32, p->d_dinv32, p->d_x32, p->d_r32, p->d_r32,
-                 p->d_p32, p->d_q32, (float*)p->d_partials, p->d_st32, p->h_st32, RP_KERNEL_SPMV32, s};
+    // FP64: r64 = b - A x and its norm; x is the FP64 solution
+    Cg<double> out = make_cg<double>(p, p->d_val64, p->d_dinv64, x, b, p->d_r, p->d_p, p->d_q, p->d_st_outer,
+                                     p->h_st_outer, RP_KERNEL_SPMV64, s);
+    // FP32 PCG on A32 d = r32 (b and r alias r32); d is folded into x
+    Cg<float> in = make_cg<float>(p, p->d_val32, p->d_dinv32, p->d_x32, p->d_r32, p->d_r32, p->d_p32, p->d_q32,
+                                  p->d_st32, p->h_st32, RP_KERNEL_SPMV32, s);
     const int chunk = std::max(1, o.check_every);
-    const float itol2 = (float)(o.inner_tol * o.inner_tol);
 
-    RP_TRY(init_state(out, 0));
     RP_TRY((launch_residual<double, true>(out, o.x0_zero != 0, p->d_r32)));
+    RP_TRY(launch_finalize(out, FIN_RESIDUAL, 0, 0.0, 0.0));
     RP_TRY(read_state(out));
     const double bb = out.h->bb;
     const double thresh = o.tol * o.tol * bb;
-    int status = RP_NOT_CONVERGED;
-    int32_t total_inner = 0, outer = 0, stall = 0;
     double rr = out.h->rr_true;
+    int status = RP_NOT_CONVERGED;
+    int32_t outer = 0, total_inner = 0, stall = 0;
     if (bb == 0.0) {
-        hipLaunchKernelGGL(fill_zero, dim3(vec_grid(n)), dim3(VEC_BLOCK), 0, s, n, x);
+        hipLaunchKernelGGL(fill_zero, dim3(out.g_vec), dim3(VEC_BLOCK), 0, s, out.n, x);
         RP_HIP_TRY(hipGetLastError());
-        status = RP_OK;
         rr = 0.0;
+        status = RP_OK;
     } else if (rr <= thresh) {
         status = RP_OK;
     }
-    while (status != RP_OK && outer < o.max_outer && total_inner < o.max_iter) {
-        ++outer;
-        RP_TRY(init_state(in, o.max_iter - total_inner));
-        RP_TRY((launch_residual<float, false>(in, true, nullptr)));
-        RP_TRY(launch_start(in, itol2));
-        RP_TRY(read_state(in));
-        RP_TRY(iterate(in, chunk));
-        total_inner += in.h->iter;
-        hipLaunchKernelGGL(ir_accumulate, dim3(vec_grid(n)), dim3(VEC_BLOCK), 0, s, n, x, p->d_x32);
+
+    // FP32 PCG from d = 0 on the current r32 (the start clears x32).
+    // reliable: never stops on its own; pauses after each update_delta
+    // reduction of its residual.  Otherwise: stops at inner_tol.
+    const float tol2_in = reliable ? 0.0f : (float)(o.inner_tol * o.inner_tol);
+    const float pause2 = reliable ? (float)(o.update_delta * o.update_delta) : 0.0f;
+    bool start_inner = true;
+    while (status != RP_OK) {
+        if (start_inner) {
+            RP_TRY((launch_residual<float, false>(in, true, nullptr)));
+            RP_TRY(launch_start(in, total_inner, tol2_in, pause2));
+            RP_TRY(read_state(in));
+            start_inner = false;
+        }
+        const int32_t it_before = in.h->iter;
+        RP_TRY(iterate(in, chunk, o.max_iter));
+        total_inner = in.h->iter;
+        const int32_t d = in.h->done;
+        // fold the FP32 correction into x and take the FP64 residual
+        hipLaunchKernelGGL(ir_accumulate, dim3(out.g_vec), dim3(VEC_BLOCK), 0, s, out.n, x, p->d_x32);
         RP_HIP_TRY(hipGetLastError());
         RP_TRY((launch_residual<double, true>(out, false, p->d_r32)));
+        RP_TRY(launch_finalize(out, FIN_RESIDUAL, 0, 0.0, 0.0));
         RP_TRY(read_state(out));
+        ++outer;
         const double rr_new = out.h->rr_true;
         if (rr_new <= thresh) {
             rr = rr_new;
             status = RP_OK;
             break;
         }
-        // no progress from the FP32 correction for three steps: give up
         stall = (rr_new > 0.25 * rr) ? stall + 1 : 0;
         rr = rr_new;
-        if (stall >= 3 || in.h->iter == 0) break;
+        if (d == CG_BREAKDOWN && in.h->iter == it_before) {
+            status = RP_ERR_BREAKDOWN;
+            set_error("FP32 CG breakdown (p.Ap = %g)", (double)in.h->pq);
+            break;
+        }
+        if (total_inner >= o.max_iter || outer >= o.max_outer || stall >= 4) break;
+        if (reliable && d == CG_PAUSED) {
+            RP_TRY(launch_resume(in));   // keep the search direction, replaced residual
+            RP_TRY(read_state(in));
+        } else {
+            start_inner = true;          // restart FP32 PCG on the new residual
+        }
     }
     info.iters = total_inner;
     info.outer_iters = outer;
@@ -446,8 +537,8 @@ int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, 
     info.rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
     info.status = status;
     if (status == RP_NOT_CONVERGED)
-        set_error("mixed refinement not converged: %d outer, %d inner iterations, relative residual %g", outer,
-                  total_inner, info.rel_res);
+        set_error("mixed solve not converged: %d FP64 updates, %d FP32 iterations, relative residual %g",
+                  outer, total_inner, info.rel_res);
     return status;
 }
 

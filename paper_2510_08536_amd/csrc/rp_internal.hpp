@@ -46,33 +46,38 @@ enum : uint32_t {
 // (upper != lower, or an interface value != its partner's)
 
 // ---------------------------------------------------------------------------
-// CG state kept on the device; S is the scalar type of the iteration
+// CG state kept on the device; S is the scalar type of the iteration.
+//
+// Reductions need no atomics or fences: a kernel leaves one partial sum per
+// block, and every block of the next kernel adds all of them in index order
+// (so all blocks hold the same scalar).  Scalars that a later kernel of the
+// same iteration still reads while block 0 stores the next value live in a
+// ring indexed by the iteration number, which the host passes to each kernel.
 // ---------------------------------------------------------------------------
 enum : int32_t {
     CG_RUNNING = 0,
     CG_CONVERGED = 1,   // recurrence residual passed the threshold
-    CG_BREAKDOWN = 2,   // p.Ap <= 0 or not finite
-    CG_MAX_ITER = 3,    // iteration budget spent
+    CG_BREAKDOWN = 2,   // p.Ap <= 0, (r, z) <= 0 or not finite
     CG_ZERO_RHS = 4,    // ||b|| = 0
+    CG_PAUSED = 5,      // residual fell below pause_thresh: FP64 update due
 };
 
 template <typename S>
 struct CgState {
-    S rz;          // (r, z) of the current residual
-    S pq;          // (p, A p)
-    S alpha;
-    S beta;
-    S rr;          // (r, r) of the current (recurrence) residual
-    S bb;          // (b, b)
-    S thresh;      // tol^2 * bb
-    S rr_true;     // (r, r) from the last explicit residual b - A x
-    int32_t iter;  // completed iterations
-    int32_t max_iter;
-    int32_t done;  // CG_*
-    int32_t pad;
-    uint32_t counter[2];  // arrival counters of the last-block reductions
+    S rz[4];        // rz[k & 3] = (r_k, M^-1 r_k)
+    S alpha, beta, pq;
+    S rr;           // (r, r) of the latest residual
+    S bb;           // (b, b)
+    S thresh;       // tol^2 * bb: convergence of the recurrence residual
+    S rr_true;      // (r, r) of the last explicit residual b - A x
+    S rr_ref;       // (r, r) when the FP32 iteration last took an FP64 update
+    S pause_frac2;  // update_delta^2 (0: never pause)
+    S pause_thresh; // pause_frac2 * rr_ref
+    int32_t iter;   // completed iterations
+    int32_t done;   // CG_*
 };
 
+// partial-sum regions of plan->d_partials (counted in elements of S)
 // kernel launch shapes
 constexpr int SPMV_BLOCK = 256;               // rows per SpMV block = threads
 constexpr int SPMV_UNROLL = 8;                // staged products per thread
@@ -138,12 +143,13 @@ struct rp_plan {
     // solver workspace
     double *d_r = nullptr, *d_p = nullptr, *d_q = nullptr;
     float *d_r32 = nullptr, *d_p32 = nullptr, *d_q32 = nullptr, *d_x32 = nullptr;
-    void* d_partials = nullptr;      // [2 * max blocks] doubles
+    void* d_partials = nullptr;      // [PART_TOTAL] doubles
     rp::CgState<double>* d_st64 = nullptr;
     rp::CgState<float>* d_st32 = nullptr;
     rp::CgState<double>* d_st_outer = nullptr;
     rp::CgState<double>* h_st64 = nullptr;   // pinned mirrors
     rp::CgState<float>* h_st32 = nullptr;
+    rp::CgState<double>* h_st_outer = nullptr;
     uint32_t* d_flags = nullptr;     // [2] error bits, asymmetry flag
     uint32_t* h_flags = nullptr;     // pinned mirror
 
@@ -155,7 +161,7 @@ namespace rp {
 
 // launch-shape helpers
 // SpMV-shaped kernels: at most SPMV_GRID_MAX blocks (a multiple of N_XCD),
-// each looping over a contiguous range of row groups.
+// block L taking row groups L, L + G, L + 2G, ...
 constexpr int SPMV_GRID_MAX = 2048;
 inline int spmv_grid(int64_t n_rows) {
     int64_t groups = (n_rows + SPMV_BLOCK - 1) / SPMV_BLOCK;
@@ -165,15 +171,19 @@ inline int spmv_grid(int64_t n_rows) {
     return (int)g;
 }
 // elementwise kernels: grid-stride loops over at most VEC_GRID_MAX blocks
-constexpr int VEC_GRID_MAX = 2048;
+constexpr int VEC_GRID_MAX = 1024;
 inline int vec_grid(int64_t n) {
     int64_t g = (n + VEC_BLOCK * 4 - 1) / (VEC_BLOCK * 4);
     if (g < 1) g = 1;
     if (g > VEC_GRID_MAX) g = VEC_GRID_MAX;
     return (int)g;
 }
-// partial sums per reduction: one per block of the larger grid
-constexpr int MAX_PARTIALS = SPMV_GRID_MAX > VEC_GRID_MAX ? SPMV_GRID_MAX : VEC_GRID_MAX;
+// partial-sum regions (in elements): two SpMV-grid ones, two vector-grid ones
+constexpr int PART_A = 0;                               // pq, or rr of b - A x
+constexpr int PART_B = SPMV_GRID_MAX;                   // bb
+constexpr int PART_RZ = 2 * SPMV_GRID_MAX;              // (r, z)
+constexpr int PART_RR = 2 * SPMV_GRID_MAX + VEC_GRID_MAX;  // (r, r)
+constexpr int PART_TOTAL = 2 * SPMV_GRID_MAX + 2 * VEC_GRID_MAX;
 
 // plan.hip
 int plan_build(rp_plan* p, const rp_rank_desc* share);
@@ -188,8 +198,10 @@ int launch_spmv32(rp_plan* p, const float* x, float* y, hipStream_t s);
 // cg.hip
 int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
                hipStream_t s);
+// reliable = true: FP32 PCG with FP64 residual replacement (RP_MIXED);
+// false: restarted FP32 inner PCG under FP64 refinement (RP_MIXED_IR)
 int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
-                hipStream_t s);
+                hipStream_t s, bool reliable);
 // grad.hip
 int launch_value_grad(rp_plan* p, const double* lambda, const double* x, double* g, hipStream_t s);
 

@@ -9,7 +9,7 @@ spmv_kernel(int32_t n_rows, const int32_t* __restrict__ row_ptr, const int32_t* 
             const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y) {
     __shared__ T lds[SPMV_CAP];
     const GroupRange gr = block_groups(n_rows);
-    for (int32_t g = gr.g0; g < gr.g1; ++g) {
+    for (int32_t g = gr.g0; g < gr.n_groups; g += gr.step) {
         const int32_t r0 = g * SPMV_BLOCK;
         const int32_t nr = min(SPMV_BLOCK, n_rows - r0);
         const T s = spmv_group_row(row_ptr, col, val, x, r0, nr, lds);

@@ -62,18 +62,19 @@ __device__ __forceinline__ T spmv_group_row(const int32_t* __restrict__ row_ptr,
     return s;
 }
 
-// Row groups handled by block L of a grid of G blocks (after xcd_block()):
-// the contiguous range [L * per, min((L + 1) * per, n_groups)).
+// Row groups of block L (after xcd_block()) in a grid of G blocks: L, L + G,
+// L + 2G, ...  At any moment the whole chip works on one window of G
+// consecutive groups, and each XCD on a contiguous eighth of it, so the x
+// entries a group gathers from neighbouring rows (a 3D stencil reaches a
+// plane away) are still in that XCD's L2.
 struct GroupRange {
-    int32_t g0, g1;
+    int32_t g0, n_groups, step;
 };
 __device__ __forceinline__ GroupRange block_groups(int32_t n_rows) {
-    const int32_t n_groups = (int32_t)(((int64_t)n_rows + SPMV_BLOCK - 1) / SPMV_BLOCK);
-    const int32_t per = (n_groups + (int32_t)gridDim.x - 1) / (int32_t)gridDim.x;
-    const int32_t L = xcd_block();
     GroupRange r;
-    r.g0 = min(L * per, n_groups);
-    r.g1 = min(r.g0 + per, n_groups);
+    r.n_groups = (int32_t)(((int64_t)n_rows + SPMV_BLOCK - 1) / SPMV_BLOCK);
+    r.g0 = xcd_block();
+    r.step = (int32_t)gridDim.x;
     return r;
 }
 

@@ -64,7 +64,8 @@ int main(void) {
   F(rp_rank_desc, n_cells); F(rp_rank_desc, n_faces); F(rp_rank_desc, owner); F(rp_rank_desc, neighbour);
   F(rp_rank_desc, n_iface); F(rp_rank_desc, iface_cell); F(rp_rank_desc, iface_nbr_rank);
   F(rp_rank_desc, iface_nbr_cell);
-  F(rp_solve_opts, tol); F(rp_solve_opts, inner_tol); F(rp_solve_opts, max_iter); F(rp_solve_opts, precision);
+  F(rp_solve_opts, tol); F(rp_solve_opts, inner_tol); F(rp_solve_opts, update_delta); F(rp_solve_opts, max_iter);
+  F(rp_solve_opts, precision);
   F(rp_solve_opts, max_outer); F(rp_solve_opts, check_every); F(rp_solve_opts, x0_zero);
   F(rp_solve_opts, max_restarts);
   F(rp_solve_info, status); F(rp_solve_info, iters); F(rp_solve_info, outer_iters); F(rp_solve_info, restarts);
@@ -90,6 +91,7 @@ def test_opts_defaults(lib_path):
     import paper_2510_08536_amd.rp as rp
     o = rp.default_opts()
     assert o.tol == 1e-8 and o.inner_tol == 1e-4 and o.precision == rp.RP_FP64 and o.check_every > 0
+    assert o.update_delta == 0.1 and o.max_outer > 0
 
 
 def test_missing_library_fails_loudly():

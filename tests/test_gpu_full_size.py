@@ -88,6 +88,9 @@ def _fp64_vs_mixed(plan, m, val64, b):
     bt = dev_tensor(b)
     x64, i64 = plan.solve(bt, tol=1e-8, precision="fp64")
     xm, im = plan.solve(bt, tol=1e-8, precision="mixed")
+    xi, ii = plan.solve(bt, tol=1e-8, precision="mixed_ir")
+    assert ii["status"] == 0 and oracle.true_relres(m, val64, b, xi.cpu().numpy()) <= 1e-8, ii
+    print(f"  mixed_ir: {ii['iters']} inner / {ii['outer_iters']} outer")
     x64h, xmh = x64.cpu().numpy(), xm.cpu().numpy()
     r64 = oracle.true_relres(m, val64, b, x64h)
     rm = oracle.true_relres(m, val64, b, xmh)
