@@ -140,6 +140,13 @@ int rp_plan_get_csr(rp_plan* plan, int32_t* row_ptr, int32_t* col, int32_t* perm
 int rp_plan_get_values(rp_plan* plan, double* val64, float* val32, double* dinv64,
                        float* dinv32);
 
+/* x windows the SpMV stages in LDS for this pattern (chosen when the plan is
+ * built from the share's face offsets): *mode = -1 none, 0 a window around
+ * the diagonal, 1 or 2: also that many pairs of windows at -d and +d rows,
+ * offsets[0..mode) = d (offsets may be NULL).  Diagnostic only: the result
+ * of rp_spmv does not depend on it. */
+int rp_plan_spmv_windows(const rp_plan* plan, int32_t* mode, int32_t* offsets);
+
 /* ---- update (Sec. 3, update procedure) --------------------------------- *
  * diag/upper/lower/iface: arrays of alpha pointers (host array), pointer s
  * giving rank first_rank+s's values in its LDU order (host or device memory).

@@ -162,7 +162,6 @@ int create(int32_t n_ranks_total, const int32_t* n_cells_all, int32_t first, int
 
     std::unique_ptr<rp_plan, void (*)(rp_plan*)> p(new (std::nothrow) rp_plan(), free_plan);
     RP_CHECK(p != nullptr, RP_ERR_ARG, "out of host memory");
-    RP_HIP_TRY(hipGetDevice(&p->device));
     p->n_ranks_total = n_ranks_total;
     p->first = first;
     p->alpha = alpha;
@@ -198,6 +197,8 @@ int create(int32_t n_ranks_total, const int32_t* n_cells_all, int32_t first, int
     }
     p->n_rows = rows;
     p->n_slots = slots;
+    // everything above is host-side validation; the GPU is touched from here on
+    RP_HIP_TRY(hipGetDevice(&p->device));
     RP_TRY(plan_build(p.get(), share));
     RP_TRY(alloc_values(p.get()));
     p->h_src.assign(4 * (size_t)alpha, nullptr);
@@ -280,6 +281,17 @@ int rp_plan_sizes(const rp_plan* p, int64_t* n_rows, int64_t* nnz_local, int64_t
     if (n_slots) *n_slots = p->n_slots;
     if (slot_off)
         for (int32_t i = 0; i <= p->alpha; ++i) slot_off[i] = p->slot_off[i];
+    return RP_OK;
+}
+
+int rp_plan_spmv_windows(const rp_plan* p, int32_t* mode, int32_t* offsets) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    if (mode) *mode = p->xw_mode;
+    if (offsets) {
+        offsets[0] = p->xw_d[0];
+        offsets[1] = p->xw_d[1];
+    }
     return RP_OK;
 }
 

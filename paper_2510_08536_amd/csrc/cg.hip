@@ -34,13 +34,14 @@ namespace {
 
 // r = b - A x (x = 0 when XZERO, and then x is cleared); with W32 also
 // r32 = RNE(r).  Partials of (r, r) -> PART_A and (b, b) -> PART_B.
-template <typename T, bool XZERO, bool W32>
+template <typename T, bool XZERO, bool W32, int NW>
 __global__ void __launch_bounds__(SPMV_BLOCK)
 residual_kernel(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                 const T* __restrict__ val, T* __restrict__ x, const T* b, T* r, float* r32,
-                T* __restrict__ part) {
+                T* __restrict__ part, XWin w) {
 #pragma clang fp contract(off)
     __shared__ T lds[XZERO ? 1 : SPMV_CAP];
+    __shared__ T xs[XZERO ? 1 : XWinSize<NW>::value];
     __shared__ T red[SPMV_BLOCK / 64];
     T prr = T(0), pbb = T(0);
     const GroupRange gr = block_groups(n);
@@ -48,7 +49,7 @@ residual_kernel(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* _
         const int32_t r0 = g * SPMV_BLOCK;
         const int32_t nr = min(SPMV_BLOCK, n - r0);
         T s = T(0);
-        if (!XZERO) s = spmv_group_row(row_ptr, col, val, x, r0, nr, lds);
+        if (!XZERO) s = spmv_group_row<T, NW>(row_ptr, col, val, x, n, r0, nr, w, xs, lds);
         if ((int32_t)threadIdx.x < nr) {
             const int32_t i = r0 + threadIdx.x;
             const T bi = b[i];
@@ -142,25 +143,26 @@ cg_finalize(int32_t mode, int32_t k, T tol2, T pause_frac2, int32_t g_spmv, int3
 }
 
 // K1: q = A p; partials of (p, q) -> PART_A
-template <typename T>
+template <typename T, int NW>
 __global__ void __launch_bounds__(SPMV_BLOCK)
 cg_spmv_pq(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
            const T* __restrict__ val, const T* __restrict__ p, T* __restrict__ q, T* __restrict__ part,
-           const CgState<T>* st) {
+           const CgState<T>* st, XWin w) {
 #pragma clang fp contract(off)
     if (st->done != CG_RUNNING) return;
     __shared__ T lds[SPMV_CAP];
+    __shared__ T xs[XWinSize<NW>::value];
     __shared__ T red[SPMV_BLOCK / 64];
     T ppq = T(0);
     const GroupRange gr = block_groups(n);
     for (int32_t g = gr.g0; g < gr.n_groups; g += gr.step) {
         const int32_t r0 = g * SPMV_BLOCK;
         const int32_t nr = min(SPMV_BLOCK, n - r0);
-        const T s = spmv_group_row(row_ptr, col, val, p, r0, nr, lds);
+        const T s = spmv_group_row<T, NW>(row_ptr, col, val, p, n, r0, nr, w, xs, lds);
         if ((int32_t)threadIdx.x < nr) {
             const int32_t i = r0 + threadIdx.x;
             q[i] = s;
-            ppq += p[i] * s;
+            ppq += own_x<T, NW>(i, xs, p) * s;
         }
     }
     const T b = block_sum<T, SPMV_BLOCK>(ppq, red);
@@ -286,13 +288,15 @@ struct Cg {
     int kernel_id;      // RP_KERNEL_SPMV64 / RP_KERNEL_SPMV32
     hipStream_t s;
     int32_t g_spmv, g_vec;
+    int32_t xw_mode;
+    XWin w;
 };
 
 template <typename T>
 Cg<T> make_cg(rp_plan* p, const T* val, const T* dinv, T* x, const T* b, T* r, T* pv, T* q, CgState<T>* st,
               CgState<T>* h, int kernel_id, hipStream_t s) {
     Cg<T> c{p, (int32_t)p->n_rows, p->d_row_ptr, p->d_col, val, dinv, x, b, r, pv, q, (T*)p->d_partials, st, h,
-            kernel_id, s, spmv_grid(p->n_rows), vec_grid(p->n_rows)};
+            kernel_id, s, spmv_grid(p->n_rows), vec_grid(p->n_rows), p->xw_mode, XWin{{p->xw_d[0], p->xw_d[1]}}};
     return c;
 }
 
@@ -306,12 +310,16 @@ int read_state(Cg<T>& c) {
 template <typename T, bool W32>
 int launch_residual(Cg<T>& c, bool xzero, float* r32) {
     const dim3 g(c.g_spmv), bl(SPMV_BLOCK);
-    if (xzero)
-        hipLaunchKernelGGL((residual_kernel<T, true, W32>), g, bl, 0, c.s, c.n, c.row_ptr, c.col, c.val, c.x,
-                           c.b, c.r, r32, c.part);
-    else
-        hipLaunchKernelGGL((residual_kernel<T, false, W32>), g, bl, 0, c.s, c.n, c.row_ptr, c.col, c.val, c.x,
-                           c.b, c.r, r32, c.part);
+    if (xzero) {
+        hipLaunchKernelGGL((residual_kernel<T, true, W32, -1>), g, bl, 0, c.s, c.n, c.row_ptr, c.col, c.val, c.x,
+                           c.b, c.r, r32, c.part, c.w);
+    } else {
+#define RP_LAUNCH(NW)                                                                                        \
+    hipLaunchKernelGGL((residual_kernel<T, false, W32, NW>), g, bl, 0, c.s, c.n, c.row_ptr, c.col, c.val, c.x, \
+                       c.b, c.r, r32, c.part, c.w)
+        RP_DISPATCH_NW(c.xw_mode, RP_LAUNCH);
+#undef RP_LAUNCH
+    }
     RP_HIP_TRY(hipGetLastError());
     return RP_OK;
 }
@@ -354,7 +362,11 @@ int iterate(Cg<T>& c, int chunk, int32_t max_iter) {
         const int32_t k1 = (int32_t)std::min<int64_t>((int64_t)k0 + chunk, max_iter);
         for (int32_t k = k0; k < k1; ++k) {
             RP_TRY(timing_begin(c.plan, c.kernel_id, c.s));
-            hipLaunchKernelGGL(cg_spmv_pq<T>, gs, bs, 0, c.s, c.n, c.row_ptr, c.col, c.val, c.p, c.q, c.part, c.st);
+#define RP_LAUNCH(NW)                                                                                          \
+    hipLaunchKernelGGL((cg_spmv_pq<T, NW>), gs, bs, 0, c.s, c.n, c.row_ptr, c.col, c.val, c.p, c.q, c.part, c.st, \
+                       c.w)
+            RP_DISPATCH_NW(c.xw_mode, RP_LAUNCH);
+#undef RP_LAUNCH
             RP_TRY(timing_end(c.plan, c.kernel_id, c.s));
             hipLaunchKernelGGL(cg_update_xr<T>, gv, bv, 0, c.s, c.n, k, c.g_spmv, c.x, c.r, c.p, c.q, c.dinv,
                                c.part, c.st);

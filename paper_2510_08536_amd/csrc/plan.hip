@@ -16,7 +16,9 @@
 // column; columns within a row are unique (a repeat is a mesh error), so the
 // result, and with it P, does not depend on the order in which the atomics
 // placed the slots.
-#include "device_util.hpp"
+#include <unordered_map>
+
+#include "spmv.hpp"
 
 namespace rp {
 
@@ -278,6 +280,41 @@ int exclusive_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* total, h
     return RP_OK;
 }
 
+// SpMV x windows: sample the share's internal faces.  The diagonal window is
+// used when at least a tenth of them couple cells at most XW_HALF apart in
+// the rank's numbering; every |neighbour - owner| offset beyond that which
+// a tenth of the faces share (at most two, most frequent first) gets a pair
+// of windows at +-d.  Interface couplings are not counted: they leave the
+// rank's numbering.
+void detect_windows(rp_plan* p, const std::vector<int32_t>& owner, const std::vector<int32_t>& nbr) {
+    p->xw_mode = -1;
+    const size_t nf = owner.size();
+    if (nf == 0) return;
+    const size_t step = std::max<size_t>(1, nf / 262144);
+    std::unordered_map<int64_t, int64_t> far;
+    int64_t samples = 0, near = 0;
+    for (size_t f = 0; f < nf; f += step) {
+        const int64_t d = std::llabs((int64_t)nbr[f] - (int64_t)owner[f]);
+        ++samples;
+        if (d <= XW_HALF) ++near;
+        else ++far[d];
+    }
+    if (10 * near < samples) return;
+    p->xw_mode = 0;
+    for (int k = 0; k < 2; ++k) {
+        int64_t best = 0, best_n = 0;
+        for (const auto& kv : far)
+            if (kv.second > best_n || (kv.second == best_n && kv.first < best)) {
+                best = kv.first;
+                best_n = kv.second;
+            }
+        if (10 * best_n < samples || best > INT32_MAX / 2) break;
+        p->xw_d[k] = (int32_t)best;
+        p->xw_mode = k + 1;
+        far.erase(best);
+    }
+}
+
 int grid_for(int64_t n, int block = 256) {
     int64_t g = (n + block - 1) / block;
     if (g < 1) g = 1;
@@ -331,6 +368,7 @@ int plan_build(rp_plan* p, const rp_rank_desc* share) {
     if ((rc = upload(&p->d_row0, p->row0.data(), A + 1))) return rc;
     if ((rc = upload(&p->d_nf, p->n_faces.data(), A))) return rc;
     if ((rc = upload(&p->d_iface_off, p->iface_off.data(), A + 1))) return rc;
+    detect_windows(p, owner, nbr);
     if ((rc = upload(&d_face_off, face_off.data(), A + 1))) return rc;
     p->d_face_off = d_face_off;
     if ((rc = upload(&d_owner, owner.data(), owner.size()))) return rc;

@@ -153,6 +153,10 @@ struct rp_plan {
     uint32_t* d_flags = nullptr;     // [2] error bits, asymmetry flag
     uint32_t* h_flags = nullptr;     // pinned mirror
 
+    // x windows of the SpMV (see spmv.hpp): -1 none, 0 diagonal, 1..2 +-d pairs
+    int32_t xw_mode = -1;
+    int32_t xw_d[2] = {0, 0};
+
     hipStream_t last_stream = nullptr;
     rp::Timing timing;
 };

@@ -3,34 +3,40 @@
 
 namespace rp {
 
-template <typename T>
+template <typename T, int NW>
 __global__ void __launch_bounds__(SPMV_BLOCK)
 spmv_kernel(int32_t n_rows, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-            const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y) {
+            const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y, XWin w) {
     __shared__ T lds[SPMV_CAP];
+    __shared__ T xs[XWinSize<NW>::value];
     const GroupRange gr = block_groups(n_rows);
     for (int32_t g = gr.g0; g < gr.n_groups; g += gr.step) {
         const int32_t r0 = g * SPMV_BLOCK;
         const int32_t nr = min(SPMV_BLOCK, n_rows - r0);
-        const T s = spmv_group_row(row_ptr, col, val, x, r0, nr, lds);
+        const T s = spmv_group_row<T, NW>(row_ptr, col, val, x, n_rows, r0, nr, w, xs, lds);
         if ((int32_t)threadIdx.x < nr) y[r0 + threadIdx.x] = s;
     }
 }
 
-int launch_spmv64(rp_plan* p, const double* x, double* y, hipStream_t s) {
+template <typename T>
+int launch_spmv(rp_plan* p, const T* val, const T* x, T* y, hipStream_t s) {
     if (p->n_rows == 0) return RP_OK;
-    hipLaunchKernelGGL(spmv_kernel<double>, dim3(spmv_grid(p->n_rows)), dim3(SPMV_BLOCK), 0, s,
-                       (int32_t)p->n_rows, p->d_row_ptr, p->d_col, p->d_val64, x, y);
+    const XWin w{{p->xw_d[0], p->xw_d[1]}};
+#define RP_LAUNCH(NW)                                                                                    \
+    hipLaunchKernelGGL((spmv_kernel<T, NW>), dim3(spmv_grid(p->n_rows)), dim3(SPMV_BLOCK), 0, s,        \
+                       (int32_t)p->n_rows, p->d_row_ptr, p->d_col, val, x, y, w)
+    RP_DISPATCH_NW(p->xw_mode, RP_LAUNCH);
+#undef RP_LAUNCH
     RP_HIP_TRY(hipGetLastError());
     return RP_OK;
 }
 
+int launch_spmv64(rp_plan* p, const double* x, double* y, hipStream_t s) {
+    return launch_spmv<double>(p, p->d_val64, x, y, s);
+}
+
 int launch_spmv32(rp_plan* p, const float* x, float* y, hipStream_t s) {
-    if (p->n_rows == 0) return RP_OK;
-    hipLaunchKernelGGL(spmv_kernel<float>, dim3(spmv_grid(p->n_rows)), dim3(SPMV_BLOCK), 0, s,
-                       (int32_t)p->n_rows, p->d_row_ptr, p->d_col, p->d_val32, x, y);
-    RP_HIP_TRY(hipGetLastError());
-    return RP_OK;
+    return launch_spmv<float>(p, p->d_val32, x, y, s);
 }
 
 }  // namespace rp

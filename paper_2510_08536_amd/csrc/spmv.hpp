@@ -1,72 +1,162 @@
-// CSR SpMV over one group of SPMV_BLOCK consecutive rows per workgroup.
+// CSR SpMV over one group of SPMV_BLOCK consecutive rows per workgroup, with
+// the x entries the group reads staged in LDS.
 //
-// The group's nonzeros form one contiguous stretch of val/col.  The block
-// streams that stretch with coalesced (non-temporal) loads, gathers x, and
-// parks each product in LDS; then every thread sums its own row's products in
-// column order.  With ~7 entries per row this keeps all 64 lanes busy on
-// loads (a thread-per-row walk would stride the stream) and needs no
-// cross-lane reduction.  Each product and each sum is rounded once, starting
-// from 0, so the result is exactly that of the serial definition.
+// Matrix stream: the group's nonzeros are one contiguous stretch of val/col.
+// The block reads it with coalesced non-temporal loads of aligned pairs (two
+// values / two column ids per lane), multiplies, parks each product in LDS,
+// and every thread then sums its own row's products in column order.  Each
+// product and each sum is rounded once, starting from 0, so the result is
+// exactly that of the serial definition.
 //
-// Groups with more than SPMV_CAP nonzeros (rows far denser than a 7-point
-// stencil) fall back to a direct per-row loop with the same arithmetic.
+// x windows: a 3D finite-volume stencil in a rank's natural cell order reads
+// x at the row itself, at +-1 and +-nx (near the diagonal) and at +-nx*ny
+// (one plane away).  Gathering those straight from global memory makes every
+// x value travel from L2 about seven times.  Instead the block copies, with
+// coalesced loads, a diagonal window x[r0 - H, r0 + 256 + H) and, per
+// dominant long-range offset d found when the plan was built, the windows
+// x[r0 - d, r0 - d + 256) and x[r0 + d, r0 + d + 256) into LDS; a column that
+// falls in none of them (processor interfaces, irregular meshes) is read from
+// global memory.  The arithmetic is unchanged, only where x comes from.
 #pragma once
 
 #include "device_util.hpp"
 
 namespace rp {
 
+constexpr int XW_HALF = 64;                          // diagonal window half-width H
+constexpr int XW_DIAG = SPMV_BLOCK + 2 * XW_HALF;    // diagonal window length
+constexpr int SPMV_PAIRS = SPMV_CAP / 2;             // staged pairs per group
+
+// window layout of a plan: NW = -1 no windows, 0 diagonal only, 1..2 plus
+// that many +-d pairs (the offsets travel as kernel arguments)
+struct XWin {
+    int32_t d[2];
+};
+
+template <int NW>
+struct XWinSize {
+    static constexpr int value = NW < 0 ? 1 : XW_DIAG + 2 * NW * SPMV_BLOCK;
+};
+
 template <typename T>
 __device__ __forceinline__ T nt_load(const T* p) {
     return __builtin_nontemporal_load(p);
 }
 
-// Returns the row sum for row r0 + threadIdx.x (0 for threads past the group).
 template <typename T>
-__device__ __forceinline__ T spmv_group_row(const int32_t* __restrict__ row_ptr,
-                                           const int32_t* __restrict__ col,
-                                           const T* __restrict__ val, const T* __restrict__ x,
-                                           int32_t r0, int32_t nr, T* lds) {
+struct Pair;
+template <>
+struct Pair<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Pair<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+typedef int32_t IdxPair __attribute__((ext_vector_type(2)));
+
+// x[c] from the LDS windows of the group starting at row r0, else from global
+template <typename T, int NW>
+__device__ __forceinline__ T x_at(int32_t c, int32_t r0, const XWin& w, const T* xs, const T* __restrict__ x) {
+    if (NW >= 0) {
+        uint32_t o = (uint32_t)(c - (r0 - XW_HALF));
+        if (o < (uint32_t)XW_DIAG) return xs[o];
+#pragma unroll
+        for (int k = 0; k < (NW > 0 ? NW : 0); ++k) {
+            o = (uint32_t)(c - (r0 - w.d[k]));
+            if (o < (uint32_t)SPMV_BLOCK) return xs[XW_DIAG + (2 * k) * SPMV_BLOCK + o];
+            o = (uint32_t)(c - (r0 + w.d[k]));
+            if (o < (uint32_t)SPMV_BLOCK) return xs[XW_DIAG + (2 * k + 1) * SPMV_BLOCK + o];
+        }
+    }
+    return x[c];
+}
+
+// Row sum for row r0 + threadIdx.x (0 for threads past the group, nr rows).
+// xs: XWinSize<NW> elements of LDS, lds: SPMV_CAP elements.  On return
+// (NW >= 0) xs[XW_HALF + t] holds x of the thread's own row.
+template <typename T, int NW>
+__device__ __forceinline__ T spmv_group_row(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                           const T* __restrict__ val, const T* __restrict__ x, int32_t n,
+                                           int32_t r0, int32_t nr, const XWin& w, T* xs, T* lds) {
 #pragma clang fp contract(off)
+    typedef typename Pair<T>::type VP;
     const int t = threadIdx.x;
     const int32_t base = row_ptr[r0];
-    const int32_t cnt = row_ptr[r0 + nr] - base;
+    const int32_t end = row_ptr[r0 + nr];
+    const int32_t al = base & ~1;                  // pairs start on an even index
+    const int32_t npairs = (end - al + 1) >> 1;
+    const bool staged = npairs <= SPMV_PAIRS;      // block-uniform
     int32_t rs = 0, re = 0;
     if (t < nr) {
         rs = row_ptr[r0 + t];
         re = row_ptr[r0 + t + 1];
     }
-    T s = T(0);
-    if (cnt <= SPMV_CAP) {
-        __syncthreads();  // the previous group may still be reading `lds`
-        int32_t c[SPMV_UNROLL];
-        T v[SPMV_UNROLL];
+    __syncthreads();  // the previous group may still be reading xs / lds
+    if (NW >= 0) {
+        for (int i = t; i < XW_DIAG; i += SPMV_BLOCK) {
+            const int32_t c = r0 - XW_HALF + i;
+            xs[i] = (c >= 0 && c < n) ? x[c] : T(0);
+        }
 #pragma unroll
-        for (int u = 0; u < SPMV_UNROLL; ++u) {
-            const int32_t j = t + u * SPMV_BLOCK;
-            if (j < cnt) {
-                c[u] = nt_load(col + base + j);
-                v[u] = nt_load(val + base + j);
+        for (int k = 0; k < (NW > 0 ? NW : 0); ++k) {
+            const int32_t cm = r0 - w.d[k] + t, cp = r0 + w.d[k] + t;
+            xs[XW_DIAG + (2 * k) * SPMV_BLOCK + t] = (cm >= 0 && cm < n) ? x[cm] : T(0);
+            xs[XW_DIAG + (2 * k + 1) * SPMV_BLOCK + t] = (cp >= 0 && cp < n) ? x[cp] : T(0);
+        }
+    }
+    constexpr int U = SPMV_PAIRS / SPMV_BLOCK;
+    IdxPair c[U];
+    VP v[U];
+    if (staged) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t k = t + u * SPMV_BLOCK;
+            if (k < npairs) {
+                if (2 * k + 2 <= end - al) {  // both entries inside [al, end): one 8/16-byte load
+                    c[u] = nt_load(reinterpret_cast<const IdxPair*>(col + al) + k);
+                    v[u] = nt_load(reinterpret_cast<const VP*>(val + al) + k);
+                } else {                       // a lone last entry
+                    c[u].x = col[al + 2 * k];
+                    v[u].x = val[al + 2 * k];
+                    c[u].y = 0;
+                    v[u].y = T(0);
+                }
             }
         }
+    }
+    __syncthreads();  // windows staged
+    if (staged) {
 #pragma unroll
-        for (int u = 0; u < SPMV_UNROLL; ++u) {
-            const int32_t j = t + u * SPMV_BLOCK;
-            if (j < cnt) lds[j] = v[u] * x[c[u]];
+        for (int u = 0; u < U; ++u) {
+            const int32_t k = t + u * SPMV_BLOCK;
+            if (k < npairs) {
+                const int32_t p0 = al + 2 * k;
+                if (p0 >= base) lds[p0 - base] = v[u].x * x_at<T, NW>(c[u].x, r0, w, xs, x);
+                if (p0 + 1 < end) lds[p0 + 1 - base] = v[u].y * x_at<T, NW>(c[u].y, r0, w, xs, x);
+            }
         }
-        __syncthreads();
+    }
+    __syncthreads();  // products staged
+    T s = T(0);
+    if (staged) {
         for (int32_t j = rs - base; j < re - base; ++j) s += lds[j];
     } else {
-        for (int32_t j = rs; j < re; ++j) s += val[j] * x[col[j]];
+        for (int32_t j = rs; j < re; ++j) s += val[j] * x_at<T, NW>(col[j], r0, w, xs, x);
     }
     return s;
 }
 
+// x of row i = r0 + threadIdx.x after spmv_group_row (from the diagonal window)
+template <typename T, int NW>
+__device__ __forceinline__ T own_x(int32_t i, const T* xs, const T* __restrict__ x) {
+    if (NW >= 0) return xs[XW_HALF + threadIdx.x];
+    return x[i];
+}
+
 // Row groups of block L (after xcd_block()) in a grid of G blocks: L, L + G,
 // L + 2G, ...  At any moment the whole chip works on one window of G
-// consecutive groups, and each XCD on a contiguous eighth of it, so the x
-// entries a group gathers from neighbouring rows (a 3D stencil reaches a
-// plane away) are still in that XCD's L2.
+// consecutive groups, and each XCD on a contiguous eighth of it.
 struct GroupRange {
     int32_t g0, n_groups, step;
 };
@@ -77,5 +167,16 @@ __device__ __forceinline__ GroupRange block_groups(int32_t n_rows) {
     r.step = (int32_t)gridDim.x;
     return r;
 }
+
+// Expand CALL(NW) for the plan's window mode.
+#define RP_DISPATCH_NW(nw, CALL)  \
+    do {                          \
+        switch (nw) {             \
+        case -1: CALL(-1); break; \
+        case 0: CALL(0); break;   \
+        case 1: CALL(1); break;   \
+        default: CALL(2); break;  \
+        }                         \
+    } while (0)
 
 }  // namespace rp

@@ -43,6 +43,7 @@ STATUS_NAMES = {0: "RP_OK", 1: "RP_NOT_CONVERGED", -1: "RP_ERR_ARG", -2: "RP_ERR
                 -6: "RP_ERR_BREAKDOWN", -7: "RP_ERR_VALUE"}
 
 EXPORTED = ["rp_plan_create", "rp_plan_destroy", "rp_plan_sizes", "rp_plan_get_csr", "rp_plan_get_values",
+            "rp_plan_spmv_windows",
             "rp_update_values", "rp_update_values_slots", "rp_spmv", "rp_solve", "rp_solve_opts_default",
             "rp_value_grad", "rp_sync", "rp_last_error", "rp_plan_set_timing", "rp_plan_kernel_stats"]
 
@@ -81,6 +82,7 @@ _sig = {
     "rp_plan_sizes": (C.c_int, [_P, _i64p, _i64p, _i64p, _i64p, _i64p]),
     "rp_plan_get_csr": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "rp_plan_get_values": (C.c_int, [_P, _P, _P, _P, _P]),
+    "rp_plan_spmv_windows": (C.c_int, [_P, _i32p, _i32p]),
     "rp_update_values": (C.c_int, [_P, _PP, _PP, _PP, _PP, _P]),
     "rp_update_values_slots": (C.c_int, [_P, _P, _P]),
     "rp_spmv": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
@@ -202,6 +204,13 @@ class Plan:
         return self._h
 
     # -- pattern / values out ---------------------------------------------
+    def spmv_windows(self):
+        """(mode, offsets) of the SpMV's LDS x windows (see include/rp.h)."""
+        mode = C.c_int32()
+        off = (C.c_int32 * 2)()
+        _check(rp_plan_spmv_windows(self._h, C.byref(mode), off), "rp_plan_spmv_windows")
+        return mode.value, [off[k] for k in range(max(mode.value, 0))]
+
     def get_csr(self):
         row_ptr = np.zeros(self.n_rows + 1, np.int32)
         col = np.zeros(max(self.nnz, 1), np.int32)

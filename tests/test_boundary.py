@@ -115,3 +115,64 @@ def test_product_does_not_touch_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "liboracle" not in text and "oracle.c" not in text, f
+
+
+def _desc(rp, n_cells, n_faces=0, n_iface=0, arr=None):
+    d = rp.rp_rank_desc()
+    d.n_cells, d.n_faces, d.n_iface = n_cells, n_faces, n_iface
+    if arr is not None:
+        p = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.owner = d.neighbour = d.iface_cell = d.iface_nbr_rank = d.iface_nbr_cell = p
+    return d
+
+
+@pytest.mark.parametrize("case", ["null_out", "no_ranks", "alpha0", "share_past_end", "first_negative",
+                                  "ncells_negative", "ncells_mismatch", "faces_negative", "owner_null",
+                                  "iface_null", "share_null"])
+def test_plan_create_rejects_bad_arguments_on_host(lib_path, case):
+    """Argument errors are caught by host-side checks before any HIP call."""
+    import numpy as np
+    import paper_2510_08536_amd.rp as rp
+    arr = np.zeros(4, np.int32)
+    nca = (ctypes.c_int32 * 2)(3, 3)
+    descs = (rp.rp_rank_desc * 2)(_desc(rp, 3, 1, 1, arr), _desc(rp, 3, 1, 1, arr))
+    out = ctypes.c_void_p()
+    args = dict(n=2, nca=nca, first=0, alpha=2, share=descs, out=ctypes.byref(out))
+    if case == "null_out":
+        args["out"] = None
+    elif case == "no_ranks":
+        args["n"] = 0
+    elif case == "alpha0":
+        args["alpha"] = 0
+    elif case == "share_past_end":
+        args["first"] = 1
+    elif case == "first_negative":
+        args["first"] = -1
+    elif case == "ncells_negative":
+        nca[1] = -1
+    elif case == "ncells_mismatch":
+        descs[1].n_cells = 4
+    elif case == "faces_negative":
+        descs[0].n_faces = -2
+    elif case == "owner_null":
+        descs[0].owner = None
+    elif case == "iface_null":
+        descs[1].iface_nbr_cell = None
+    elif case == "share_null":
+        args["share"] = None
+    rc = rp.rp_plan_create(args["n"], nca, args["first"], args["alpha"], args["share"], args["out"])
+    assert rc == rp.RP_ERR_ARG, (case, rc, rp.rp_last_error())
+    assert rp.rp_last_error()
+
+
+def test_plan_create_rejects_overflow_on_host(lib_path):
+    """A share whose slots reach 2^31 is refused before anything is allocated."""
+    import numpy as np
+    import paper_2510_08536_amd.rp as rp
+    arr = np.zeros(4, np.int32)
+    big = 700_000_000          # 3 ranks x (n + 2 * faces) > 2^31 slots
+    nca = (ctypes.c_int32 * 3)(big, big, big)
+    descs = (rp.rp_rank_desc * 3)(*[_desc(rp, big, big // 2, 0, arr) for _ in range(3)])
+    out = ctypes.c_void_p()
+    rc = rp.rp_plan_create(3, nca, 0, 3, descs, ctypes.byref(out))
+    assert rc == rp.RP_ERR_OVERFLOW and out.value is None

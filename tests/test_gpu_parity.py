@@ -26,6 +26,8 @@ CASES = {
     "slabs_c1like": ((32, 32, 32), ("blocks", 1, 1, 4), dict()),
     "one_cell_per_rank": ((9, 1, 1), ("blocks", 9, 1, 1), dict(walls=(True, False, False))),
     "single_rank": ((7, 6, 5), ("blocks", 1, 1, 1), dict(kappa=(1e-2, 1.0), scramble=True)),
+    "two_pairs": ((80, 3, 5), ("blocks", 1, 1, 1), dict(kappa=(1e-2, 1.0))),
+    "banded_ragged": ((20, 9, 31), ("blocks", 1, 2, 3), dict(kappa=(1e-2, 1.0))),
 }
 
 
@@ -128,7 +130,30 @@ def test_update_slots_bit_exact():
     del torch
 
 
-@pytest.mark.parametrize("name", ["ragged_rcb7", "slabs_c1like", "stretched_rcb", "one_cell_per_rank"])
+def test_spmv_window_detection():
+    """The plan finds the long-range stencil offset of blocked natural
+    numbering (nx * ny of the rank block) and no windows for scrambled ids."""
+    expect = {"slabs_c1like": (1, [1024]), "chain8_4": (0, [])}
+    for name, want in expect.items():
+        plan = make_plan(_work(name))
+        assert plan.spmv_windows() == want, name
+        plan.close()
+    w = synth.small((30, 30, 30), ("rcb", 3), seed=2, scramble=True)   # random local order
+    plan = make_plan(w)
+    assert plan.spmv_windows() == (-1, [])
+    plan.close()
+    w = synth.small((20, 8, 12), ("blocks", 1, 1, 2), seed=1)    # nx = 20 <= 64, nx*ny = 160
+    plan = make_plan(w)
+    assert plan.spmv_windows() == (1, [160])
+    plan.close()
+    w = synth.small((80, 3, 4), ("blocks", 1, 1, 1), seed=1)     # nx = 80 > 64: two pairs,
+    plan = make_plan(w)                                            # the more frequent first
+    assert plan.spmv_windows() == (2, [240, 80])
+    plan.close()
+
+
+@pytest.mark.parametrize("name", ["ragged_rcb7", "slabs_c1like", "stretched_rcb", "one_cell_per_rank",
+                                  "single_rank", "chain8_4", "two_pairs", "banded_ragged"])
 def test_spmv_fp64_bit_exact(name):
     w = _work(name, seed=7)
     m, buf, val64, val32, *_ = oracle_system(w)
@@ -141,7 +166,7 @@ def test_spmv_fp64_bit_exact(name):
     plan.close()
 
 
-@pytest.mark.parametrize("name", ["ragged_rcb7", "slabs_c1like"])
+@pytest.mark.parametrize("name", ["ragged_rcb7", "slabs_c1like", "two_pairs", "banded_ragged"])
 def test_spmv_fp32_error_bound(name):
     """FP32 SpMV: each row sums k products with one rounding each, so
     |y32 - y| <= gamma_{k+1} * sum |a_ij x_j| with gamma_m = m u / (1 - m u),
