@@ -140,12 +140,15 @@ int rp_plan_get_csr(rp_plan* plan, int32_t* row_ptr, int32_t* col, int32_t* perm
 int rp_plan_get_values(rp_plan* plan, double* val64, float* val32, double* dinv64,
                        float* dinv32);
 
-/* x windows the SpMV stages in LDS for this pattern (chosen when the plan is
- * built from the share's face offsets): *mode = -1 none, 0 a window around
- * the diagonal, 1 or 2: also that many pairs of windows at -d and +d rows,
- * offsets[0..mode) = d (offsets may be NULL).  Diagnostic only: the result
- * of rp_spmv does not depend on it. */
-int rp_plan_spmv_windows(const rp_plan* plan, int32_t* mode, int32_t* offsets);
+/* LDS x windows of the SpMV.  When the plan is built, the share's face
+ * offsets give a window layout: *mode = -1 none, 0 a window around the
+ * diagonal, 1 or 2: also that many pairs of windows at -d and +d rows,
+ * offsets[0..mode) = d.  *enabled says whether the SpMV kernels stage x
+ * through those windows (off by default: on MI355X the direct x loads
+ * measured faster).  Any output may be NULL.  Results of every kernel are
+ * identical either way; only where x is read from changes. */
+int rp_plan_spmv_windows(const rp_plan* plan, int32_t* mode, int32_t* offsets, int32_t* enabled);
+int rp_plan_set_spmv_windows(rp_plan* plan, int32_t enable);
 
 /* ---- update (Sec. 3, update procedure) --------------------------------- *
  * diag/upper/lower/iface: arrays of alpha pointers (host array), pointer s

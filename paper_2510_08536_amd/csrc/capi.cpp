@@ -284,14 +284,22 @@ int rp_plan_sizes(const rp_plan* p, int64_t* n_rows, int64_t* nnz_local, int64_t
     return RP_OK;
 }
 
-int rp_plan_spmv_windows(const rp_plan* p, int32_t* mode, int32_t* offsets) {
+int rp_plan_spmv_windows(const rp_plan* p, int32_t* mode, int32_t* offsets, int32_t* enabled) {
     clear_error();
     RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
-    if (mode) *mode = p->xw_mode;
+    if (mode) *mode = p->xw_found;
     if (offsets) {
         offsets[0] = p->xw_d[0];
         offsets[1] = p->xw_d[1];
     }
+    if (enabled) *enabled = p->xw_mode == p->xw_found && p->xw_found >= 0;
+    return RP_OK;
+}
+
+int rp_plan_set_spmv_windows(rp_plan* p, int32_t enable) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    p->xw_mode = enable ? p->xw_found : -1;
     return RP_OK;
 }
 

@@ -287,6 +287,7 @@ int exclusive_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* total, h
 // of windows at +-d.  Interface couplings are not counted: they leave the
 // rank's numbering.
 void detect_windows(rp_plan* p, const std::vector<int32_t>& owner, const std::vector<int32_t>& nbr) {
+    p->xw_found = -1;
     p->xw_mode = -1;
     const size_t nf = owner.size();
     if (nf == 0) return;
@@ -300,7 +301,7 @@ void detect_windows(rp_plan* p, const std::vector<int32_t>& owner, const std::ve
         else ++far[d];
     }
     if (10 * near < samples) return;
-    p->xw_mode = 0;
+    p->xw_found = 0;
     for (int k = 0; k < 2; ++k) {
         int64_t best = 0, best_n = 0;
         for (const auto& kv : far)
@@ -310,7 +311,7 @@ void detect_windows(rp_plan* p, const std::vector<int32_t>& owner, const std::ve
             }
         if (10 * best_n < samples || best > INT32_MAX / 2) break;
         p->xw_d[k] = (int32_t)best;
-        p->xw_mode = k + 1;
+        p->xw_found = k + 1;
         far.erase(best);
     }
 }

@@ -153,7 +153,9 @@ struct rp_plan {
     uint32_t* d_flags = nullptr;     // [2] error bits, asymmetry flag
     uint32_t* h_flags = nullptr;     // pinned mirror
 
-    // x windows of the SpMV (see spmv.hpp): -1 none, 0 diagonal, 1..2 +-d pairs
+    // x windows of the SpMV (see spmv.hpp): -1 none, 0 diagonal, 1..2 +-d pairs;
+    // xw_mode is what the kernels use: xw_found when enabled, else -1
+    int32_t xw_found = -1;
     int32_t xw_mode = -1;
     int32_t xw_d[2] = {0, 0};
 
@@ -166,7 +168,7 @@ namespace rp {
 // launch-shape helpers
 // SpMV-shaped kernels: at most SPMV_GRID_MAX blocks (a multiple of N_XCD),
 // block L taking row groups L, L + G, L + 2G, ...
-constexpr int SPMV_GRID_MAX = 2048;
+constexpr int SPMV_GRID_MAX = 1536;
 inline int spmv_grid(int64_t n_rows) {
     int64_t groups = (n_rows + SPMV_BLOCK - 1) / SPMV_BLOCK;
     int64_t g = ((groups + N_XCD - 1) / N_XCD) * N_XCD;

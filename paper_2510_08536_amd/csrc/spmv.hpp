@@ -1,5 +1,4 @@
-// CSR SpMV over one group of SPMV_BLOCK consecutive rows per workgroup, with
-// the x entries the group reads staged in LDS.
+// CSR SpMV over one group of SPMV_BLOCK consecutive rows per workgroup.
 //
 // Matrix stream: the group's nonzeros are one contiguous stretch of val/col.
 // The block reads it with coalesced non-temporal loads of aligned pairs (two
@@ -8,15 +7,17 @@
 // product and each sum is rounded once, starting from 0, so the result is
 // exactly that of the serial definition.
 //
-// x windows: a 3D finite-volume stencil in a rank's natural cell order reads
-// x at the row itself, at +-1 and +-nx (near the diagonal) and at +-nx*ny
-// (one plane away).  Gathering those straight from global memory makes every
-// x value travel from L2 about seven times.  Instead the block copies, with
-// coalesced loads, a diagonal window x[r0 - H, r0 + 256 + H) and, per
-// dominant long-range offset d found when the plan was built, the windows
-// x[r0 - d, r0 - d + 256) and x[r0 + d, r0 + d + 256) into LDS; a column that
-// falls in none of them (processor interfaces, irregular meshes) is read from
-// global memory.  The arithmetic is unchanged, only where x comes from.
+// x: by default every product's x entry is loaded straight from global
+// memory, all of a thread's loads issued before the first product so they
+// are in flight together.  Optionally (rp_plan_set_spmv_windows) x is staged
+// in LDS windows instead: a 3D finite-volume stencil in a rank's natural
+// cell order reads x at the row, at +-1 and +-nx (near the diagonal) and at
+// +-nx*ny (a plane away), so the block copies a diagonal window
+// x[r0 - H, r0 + 256 + H) and, per dominant long-range offset d found when
+// the plan was built, x[r0 -+ d, r0 -+ d + 256) with coalesced loads; other
+// columns are read from global memory.  On MI355X the direct loads measured
+// faster (the HBM bytes are the same; the staging costs LDS, a barrier and
+// occupancy), hence the default.  The arithmetic is the same either way.
 #pragma once
 
 #include "device_util.hpp"
@@ -108,6 +109,11 @@ __device__ __forceinline__ T spmv_group_row(const int32_t* __restrict__ row_ptr,
     constexpr int U = SPMV_PAIRS / SPMV_BLOCK;
     IdxPair c[U];
     VP v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        c[u] = IdxPair{0, 0};
+        v[u] = VP{T(0), T(0)};
+    }
     if (staged) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -125,8 +131,27 @@ __device__ __forceinline__ T spmv_group_row(const int32_t* __restrict__ row_ptr,
             }
         }
     }
+    if (NW < 0 && staged) {
+        // direct x: issue all gathers before any product so they are in
+        // flight together (lanes without entries hold column 0)
+        T gx[2 * U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            gx[2 * u] = x[c[u].x];
+            gx[2 * u + 1] = x[c[u].y];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t k = t + u * SPMV_BLOCK;
+            if (k < npairs) {
+                const int32_t p0 = al + 2 * k;
+                if (p0 >= base) lds[p0 - base] = v[u].x * gx[2 * u];
+                if (p0 + 1 < end) lds[p0 + 1 - base] = v[u].y * gx[2 * u + 1];
+            }
+        }
+    }
     __syncthreads();  // windows staged
-    if (staged) {
+    if (NW >= 0 && staged) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int32_t k = t + u * SPMV_BLOCK;
@@ -137,7 +162,7 @@ __device__ __forceinline__ T spmv_group_row(const int32_t* __restrict__ row_ptr,
             }
         }
     }
-    __syncthreads();  // products staged
+    __syncthreads();  // products staged (the direct path wrote them before the previous barrier)
     T s = T(0);
     if (staged) {
         for (int32_t j = rs - base; j < re - base; ++j) s += lds[j];

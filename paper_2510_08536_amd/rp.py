@@ -43,7 +43,7 @@ STATUS_NAMES = {0: "RP_OK", 1: "RP_NOT_CONVERGED", -1: "RP_ERR_ARG", -2: "RP_ERR
                 -6: "RP_ERR_BREAKDOWN", -7: "RP_ERR_VALUE"}
 
 EXPORTED = ["rp_plan_create", "rp_plan_destroy", "rp_plan_sizes", "rp_plan_get_csr", "rp_plan_get_values",
-            "rp_plan_spmv_windows",
+            "rp_plan_spmv_windows", "rp_plan_set_spmv_windows",
             "rp_update_values", "rp_update_values_slots", "rp_spmv", "rp_solve", "rp_solve_opts_default",
             "rp_value_grad", "rp_sync", "rp_last_error", "rp_plan_set_timing", "rp_plan_kernel_stats"]
 
@@ -82,7 +82,8 @@ _sig = {
     "rp_plan_sizes": (C.c_int, [_P, _i64p, _i64p, _i64p, _i64p, _i64p]),
     "rp_plan_get_csr": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "rp_plan_get_values": (C.c_int, [_P, _P, _P, _P, _P]),
-    "rp_plan_spmv_windows": (C.c_int, [_P, _i32p, _i32p]),
+    "rp_plan_spmv_windows": (C.c_int, [_P, _i32p, _i32p, _i32p]),
+    "rp_plan_set_spmv_windows": (C.c_int, [_P, C.c_int32]),
     "rp_update_values": (C.c_int, [_P, _PP, _PP, _PP, _PP, _P]),
     "rp_update_values_slots": (C.c_int, [_P, _P, _P]),
     "rp_spmv": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
@@ -205,11 +206,19 @@ class Plan:
 
     # -- pattern / values out ---------------------------------------------
     def spmv_windows(self):
-        """(mode, offsets) of the SpMV's LDS x windows (see include/rp.h)."""
-        mode = C.c_int32()
+        """(mode, offsets) of the LDS x-window layout found for this pattern."""
+        mode, en = C.c_int32(), C.c_int32()
         off = (C.c_int32 * 2)()
-        _check(rp_plan_spmv_windows(self._h, C.byref(mode), off), "rp_plan_spmv_windows")
+        _check(rp_plan_spmv_windows(self._h, C.byref(mode), off, C.byref(en)), "rp_plan_spmv_windows")
         return mode.value, [off[k] for k in range(max(mode.value, 0))]
+
+    def spmv_windows_enabled(self) -> bool:
+        en = C.c_int32()
+        _check(rp_plan_spmv_windows(self._h, None, None, C.byref(en)), "rp_plan_spmv_windows")
+        return bool(en.value)
+
+    def set_spmv_windows(self, enable: bool):
+        _check(rp_plan_set_spmv_windows(self._h, int(bool(enable))), "rp_plan_set_spmv_windows")
 
     def get_csr(self):
         row_ptr = np.zeros(self.n_rows + 1, np.int32)

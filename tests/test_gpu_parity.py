@@ -154,20 +154,25 @@ def test_spmv_window_detection():
 
 @pytest.mark.parametrize("name", ["ragged_rcb7", "slabs_c1like", "stretched_rcb", "one_cell_per_rank",
                                   "single_rank", "chain8_4", "two_pairs", "banded_ragged"])
-def test_spmv_fp64_bit_exact(name):
+@pytest.mark.parametrize("windows", [False, True])
+def test_spmv_fp64_bit_exact(name, windows):
     w = _work(name, seed=7)
     m, buf, val64, val32, *_ = oracle_system(w)
     plan = make_plan(w)
+    assert not plan.spmv_windows_enabled()
+    plan.set_spmv_windows(windows)
+    assert plan.spmv_windows_enabled() == (windows and plan.spmv_windows()[0] >= 0)
     update(plan, share_values(w))
     rng = np.random.default_rng(2)
     for x in (rng.uniform(-1, 1, m.n_rows), rng.standard_normal(m.n_rows) * 1e3, np.zeros(m.n_rows)):
         y = plan.spmv(dev_tensor(x)).cpu().numpy()
-        assert_bits_equal(y, oracle.spmv(m, val64, x), f"{name} spmv64")
+        assert_bits_equal(y, oracle.spmv(m, val64, x), f"{name} spmv64 windows={windows}")
     plan.close()
 
 
 @pytest.mark.parametrize("name", ["ragged_rcb7", "slabs_c1like", "two_pairs", "banded_ragged"])
-def test_spmv_fp32_error_bound(name):
+@pytest.mark.parametrize("windows", [False, True])
+def test_spmv_fp32_error_bound(name, windows):
     """FP32 SpMV: each row sums k products with one rounding each, so
     |y32 - y| <= gamma_{k+1} * sum |a_ij x_j| with gamma_m = m u / (1 - m u),
     u = 2^-24, against the exact (FP64) product of the same FP32 inputs."""
@@ -175,6 +180,7 @@ def test_spmv_fp32_error_bound(name):
     w = _work(name, seed=9)
     m, buf, val64, val32, *_ = oracle_system(w)
     plan = make_plan(w)
+    plan.set_spmv_windows(windows)
     update(plan, share_values(w))
     x32 = np.random.default_rng(4).uniform(-1, 1, m.n_rows).astype(np.float32)
     y = plan.spmv(dev_tensor(x32)).cpu().numpy().astype(np.float64)

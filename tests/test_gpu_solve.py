@@ -104,6 +104,20 @@ def test_deterministic_and_chunk_independent():
     plan.close()
 
 
+def test_windows_do_not_change_solves():
+    """Staging x through LDS windows changes where x is read, not the result:
+    FP64 and mixed solves are bit-identical either way."""
+    w, m, val64, plan = _setup("c1")
+    b = dev_tensor(w.rhs())
+    for prec in ("fp64", "mixed"):
+        plan.set_spmv_windows(False)
+        x0, i0 = plan.solve(b, precision=prec)
+        plan.set_spmv_windows(True)
+        x1, i1 = plan.solve(b, precision=prec)
+        assert i0["iters"] == i1["iters"] and torch_mod().equal(x0, x1), prec
+    plan.close()
+
+
 def test_zero_rhs_and_warm_start():
     torch = torch_mod()
     w, m, val64, plan = _setup("stretched")
