@@ -51,6 +51,25 @@ def parse():
     return ap.parse_args()
 
 
+def profiled_traffic(config):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (profiles/traffic_<config>.md), or None when there is none or the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"traffic_{config}.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"traffic_bytes_per_launch: (\d+); kernel: [^;]+; sources_sha256_16: ([0-9a-f]+)",
+                  open(path).read())
+    if not m:
+        return None
+    h = hashlib.sha256()
+    for f in ("spmv.hpp", "cg.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2510_08536_amd", "csrc", f), "rb").read())
+    return int(m.group(1)) if h.hexdigest()[:16] == m.group(2) else None
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -229,7 +248,9 @@ def main():
                      "achieved": round(spmv_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(spmv_gbs / HBM_PEAK_GBS, 4),
                      "bytes_per_launch": spmv64_bytes, "avg_launch_ms": round(spmv_avg_ms, 5),
-                     "launches": n_spmv, "traffic": None},
+                     "launches": n_spmv, "traffic": profiled_traffic(a.config),
+                     "traffic_note": "HBM bytes/launch from FETCH_SIZE+WRITE_SIZE (profiles/traffic_c3.md), "
+                                     "scaled by a 2 GiB copy; null if the kernel changed since"},
     }
 
     if not a.no_cpu_baseline:
