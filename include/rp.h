@@ -150,6 +150,30 @@ int rp_plan_get_values(rp_plan* plan, double* val64, float* val32, double* dinv6
 int rp_plan_spmv_windows(const rp_plan* plan, int32_t* mode, int32_t* offsets, int32_t* enabled);
 int rp_plan_set_spmv_windows(rp_plan* plan, int32_t enable);
 
+/* Column-index form of the SpMV.  When the plan is built, every group of 256
+ * consecutive fused rows whose entries use at most 16 distinct offsets
+ * col - row (a stencil in a rank's natural cell order) is offset-coded: the
+ * SpMV kernels keep its CSR values but take the columns from one ascending
+ * offset table per group and a 16-bit mask per row instead of reading col;
+ * every other group (scrambled numbering, many offsets) is read as CSR.
+ * Products and row sums are formed in the same order either way, so every
+ * result is identical; only the bytes read change.  bytes64 / bytes32 are
+ * the algorithmic HBM bytes of one y = A x in the form in use (each value,
+ * index word, x and y element once). */
+typedef struct rp_spmv_format {
+    int32_t enabled;       /* the kernels use the coded groups (default 1) */
+    int32_t reserved;
+    int64_t n_groups;      /* groups of 256 rows */
+    int64_t coded_groups;  /* groups that are offset-coded */
+    int64_t coded_rows;
+    int64_t coded_nnz;
+    int64_t bytes64;
+    int64_t bytes32;
+} rp_spmv_format;
+int rp_plan_spmv_format(const rp_plan* plan, rp_spmv_format* info);
+/* enable = 0: every group as CSR; 1: coded groups where built (default). */
+int rp_plan_set_spmv_format(rp_plan* plan, int32_t enable);
+
 /* ---- update (Sec. 3, update procedure) --------------------------------- *
  * diag/upper/lower/iface: arrays of alpha pointers (host array), pointer s
  * giving rank first_rank+s's values in its LDU order (host or device memory).

@@ -75,7 +75,7 @@ void free_plan(rp_plan* p) {
                    p->d_perm, p->d_perm_inv, p->d_nl_row_ptr, p->d_nl_col, p->d_iface_partner, p->d_recv,
                    p->d_val64, p->d_val32, p->d_dinv64, p->d_dinv32, p->d_r, p->d_p, p->d_q, p->d_r32,
                    p->d_p32, p->d_q32, p->d_x32, p->d_partials, p->d_st64, p->d_st32, p->d_st_outer,
-                   p->d_flags};
+                   p->d_flags, p->d_goi_k, p->d_goi_off, p->d_goi_mask};
     for (void* q : dev)
         if (q) (void)hipFree(q);
     if (p->h_st64) (void)hipHostFree(p->h_st64);
@@ -98,8 +98,11 @@ int dalloc(T** q, int64_t count) {
 int alloc_values(rp_plan* p) {
     const int64_t n = p->n_rows, ns = p->n_slots;
     RP_TRY(dalloc(&p->d_recv, ns));
-    RP_TRY(dalloc(&p->d_val64, ns));
-    RP_TRY(dalloc(&p->d_val32, ns));
+    // SpMV pair loads may touch SPMV_PAD elements past the values
+    RP_TRY(dalloc(&p->d_val64, ns + SPMV_PAD));
+    RP_TRY(dalloc(&p->d_val32, ns + SPMV_PAD));
+    RP_HIP_TRY(hipMemset(p->d_val64 + ns, 0, sizeof(double) * SPMV_PAD));
+    RP_HIP_TRY(hipMemset(p->d_val32 + ns, 0, sizeof(float) * SPMV_PAD));
     RP_TRY(dalloc(&p->d_dinv64, n));
     RP_TRY(dalloc(&p->d_dinv32, n));
     RP_TRY(dalloc(&p->d_r, n));
@@ -300,6 +303,38 @@ int rp_plan_set_spmv_windows(rp_plan* p, int32_t enable) {
     clear_error();
     RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
     p->xw_mode = enable ? p->xw_found : -1;
+    return RP_OK;
+}
+
+int rp_plan_spmv_format(const rp_plan* p, rp_spmv_format* info) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    RP_CHECK(info != nullptr, RP_ERR_ARG, "info is NULL");
+    const bool coded = p->goi_on && p->coded_groups > 0;
+    const int64_t n = p->n_rows;
+    const int64_t cg = coded ? p->coded_groups : 0, cr = coded ? p->coded_rows : 0, cn = coded ? p->coded_nnz : 0;
+    // values, index words (coded: mask per row, k + offset table and the
+    // first row pointer per group; CSR: col per entry, row pointer per row),
+    // x read once, y written once, the closing row pointer
+    auto bytes = [&](int64_t sv) {
+        return cn * sv + 2 * cr + 4 * (1 + rp::GOI_KMAX) * cg + 4 * cg + (p->nnz - cn) * (sv + 4) + 4 * (n - cr) +
+               2 * n * sv + 4;
+    };
+    info->enabled = p->goi_on;
+    info->reserved = 0;
+    info->n_groups = p->n_groups;
+    info->coded_groups = p->coded_groups;
+    info->coded_rows = p->coded_rows;
+    info->coded_nnz = p->coded_nnz;
+    info->bytes64 = bytes(8);
+    info->bytes32 = bytes(4);
+    return RP_OK;
+}
+
+int rp_plan_set_spmv_format(rp_plan* p, int32_t enable) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    p->goi_on = enable ? 1 : 0;
     return RP_OK;
 }
 

@@ -36,11 +36,10 @@ namespace {
 // r32 = RNE(r).  Partials of (r, r) -> PART_A and (b, b) -> PART_B.
 template <typename T, bool XZERO, bool W32, int NW>
 __global__ void __launch_bounds__(SPMV_BLOCK)
-residual_kernel(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                const T* __restrict__ val, T* __restrict__ x, const T* b, T* r, float* r32,
-                T* __restrict__ part, XWin w) {
+residual_kernel(int32_t n, SpmvIdx ix, const T* __restrict__ val, T* __restrict__ x, const T* b, T* r,
+                float* r32, T* __restrict__ part, XWin w) {
 #pragma clang fp contract(off)
-    __shared__ T lds[XZERO ? 1 : SPMV_CAP];
+    __shared__ __align__(16) T lds[XZERO ? 2 : SPMV_CAP];
     __shared__ T xs[XZERO ? 1 : XWinSize<NW>::value];
     __shared__ T red[SPMV_BLOCK / 64];
     T prr = T(0), pbb = T(0);
@@ -49,7 +48,7 @@ residual_kernel(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* _
         const int32_t r0 = g * SPMV_BLOCK;
         const int32_t nr = min(SPMV_BLOCK, n - r0);
         T s = T(0);
-        if (!XZERO) s = spmv_group_row<T, NW>(row_ptr, col, val, x, n, r0, nr, w, xs, lds);
+        if (!XZERO) s = spmv_group_row<T, NW>(ix, val, x, n, g, nr, w, xs, lds).s;
         if ((int32_t)threadIdx.x < nr) {
             const int32_t i = r0 + threadIdx.x;
             const T bi = b[i];
@@ -145,12 +144,11 @@ cg_finalize(int32_t mode, int32_t k, T tol2, T pause_frac2, int32_t g_spmv, int3
 // K1: q = A p; partials of (p, q) -> PART_A
 template <typename T, int NW>
 __global__ void __launch_bounds__(SPMV_BLOCK)
-cg_spmv_pq(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-           const T* __restrict__ val, const T* __restrict__ p, T* __restrict__ q, T* __restrict__ part,
-           const CgState<T>* st, XWin w) {
+cg_spmv_pq(int32_t n, SpmvIdx ix, const T* __restrict__ val, const T* __restrict__ p, T* __restrict__ q,
+           T* __restrict__ part, const CgState<T>* st, XWin w) {
 #pragma clang fp contract(off)
     if (st->done != CG_RUNNING) return;
-    __shared__ T lds[SPMV_CAP];
+    __shared__ __align__(16) T lds[SPMV_CAP];
     __shared__ T xs[XWinSize<NW>::value];
     __shared__ T red[SPMV_BLOCK / 64];
     T ppq = T(0);
@@ -158,11 +156,11 @@ cg_spmv_pq(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __rest
     for (int32_t g = gr.g0; g < gr.n_groups; g += gr.step) {
         const int32_t r0 = g * SPMV_BLOCK;
         const int32_t nr = min(SPMV_BLOCK, n - r0);
-        const T s = spmv_group_row<T, NW>(row_ptr, col, val, p, n, r0, nr, w, xs, lds);
+        const GroupRow<T> gr_ = spmv_group_row<T, NW>(ix, val, p, n, g, nr, w, xs, lds);
         if ((int32_t)threadIdx.x < nr) {
             const int32_t i = r0 + threadIdx.x;
-            q[i] = s;
-            ppq += own_x<T, NW>(i, xs, p) * s;
+            q[i] = gr_.s;
+            ppq += own_x<T, NW>(i, gr_.coded, xs, p) * gr_.s;
         }
     }
     const T b = block_sum<T, SPMV_BLOCK>(ppq, red);
@@ -273,8 +271,7 @@ template <typename T>
 struct Cg {
     rp_plan* plan;
     int32_t n;
-    const int32_t* row_ptr;
-    const int32_t* col;
+    SpmvIdx ix;
     const T* val;
     const T* dinv;
     T* x;
@@ -295,7 +292,7 @@ struct Cg {
 template <typename T>
 Cg<T> make_cg(rp_plan* p, const T* val, const T* dinv, T* x, const T* b, T* r, T* pv, T* q, CgState<T>* st,
               CgState<T>* h, int kernel_id, hipStream_t s) {
-    Cg<T> c{p, (int32_t)p->n_rows, p->d_row_ptr, p->d_col, val, dinv, x, b, r, pv, q, (T*)p->d_partials, st, h,
+    Cg<T> c{p, (int32_t)p->n_rows, spmv_idx(p), val, dinv, x, b, r, pv, q, (T*)p->d_partials, st, h,
             kernel_id, s, spmv_grid(p->n_rows), vec_grid(p->n_rows), p->xw_mode, XWin{{p->xw_d[0], p->xw_d[1]}}};
     return c;
 }
@@ -311,11 +308,11 @@ template <typename T, bool W32>
 int launch_residual(Cg<T>& c, bool xzero, float* r32) {
     const dim3 g(c.g_spmv), bl(SPMV_BLOCK);
     if (xzero) {
-        hipLaunchKernelGGL((residual_kernel<T, true, W32, -1>), g, bl, 0, c.s, c.n, c.row_ptr, c.col, c.val, c.x,
+        hipLaunchKernelGGL((residual_kernel<T, true, W32, -1>), g, bl, 0, c.s, c.n, c.ix, c.val, c.x,
                            c.b, c.r, r32, c.part, c.w);
     } else {
 #define RP_LAUNCH(NW)                                                                                        \
-    hipLaunchKernelGGL((residual_kernel<T, false, W32, NW>), g, bl, 0, c.s, c.n, c.row_ptr, c.col, c.val, c.x, \
+    hipLaunchKernelGGL((residual_kernel<T, false, W32, NW>), g, bl, 0, c.s, c.n, c.ix, c.val, c.x, \
                        c.b, c.r, r32, c.part, c.w)
         RP_DISPATCH_NW(c.xw_mode, RP_LAUNCH);
 #undef RP_LAUNCH
@@ -363,7 +360,7 @@ int iterate(Cg<T>& c, int chunk, int32_t max_iter) {
         for (int32_t k = k0; k < k1; ++k) {
             RP_TRY(timing_begin(c.plan, c.kernel_id, c.s));
 #define RP_LAUNCH(NW)                                                                                          \
-    hipLaunchKernelGGL((cg_spmv_pq<T, NW>), gs, bs, 0, c.s, c.n, c.row_ptr, c.col, c.val, c.p, c.q, c.part, c.st, \
+    hipLaunchKernelGGL((cg_spmv_pq<T, NW>), gs, bs, 0, c.s, c.n, c.ix, c.val, c.p, c.q, c.part, c.st, \
                        c.w)
             RP_DISPATCH_NW(c.xw_mode, RP_LAUNCH);
 #undef RP_LAUNCH

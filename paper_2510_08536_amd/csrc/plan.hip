@@ -16,6 +16,7 @@
 // column; columns within a row are unique (a repeat is a mesh error), so the
 // result, and with it P, does not depend on the order in which the atomics
 // placed the slots.
+#include <algorithm>
 #include <unordered_map>
 
 #include "spmv.hpp"
@@ -339,6 +340,124 @@ struct TempFree {
 
 }  // namespace
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// offset-coded SpMV index (the form is described in spmv.hpp)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int32_t block_min_i32(int32_t v, int32_t* red) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    __syncthreads();  // red free from the previous call
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int32_t r = red[0];
+    for (int w = 1; w < SPMV_BLOCK / 64; ++w) r = min(r, red[w]);
+    return r;
+}
+
+// One block per group of SPMV_BLOCK rows (columns already sorted per row).
+// The distinct offsets col - row of the group are found smallest first, one
+// block-wide minimum per offset; a group with more than GOI_KMAX of them, or
+// whose values span more than SPMV_CAP / 2 aligned pairs, stays CSR (k = 0).
+__global__ void __launch_bounds__(SPMV_BLOCK)
+goi_encode(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+           int32_t* __restrict__ goi_k, int32_t* __restrict__ goi_off, uint16_t* __restrict__ goi_mask) {
+    __shared__ int32_t red[SPMV_BLOCK / 64];
+    __shared__ int32_t tab[GOI_KMAX];
+    const int32_t g = blockIdx.x, t = threadIdx.x;
+    const int32_t r0 = g * SPMV_BLOCK, nr = min(SPMV_BLOCK, n - r0), i = r0 + t;
+    int32_t rs = 0, re = 0;
+    if (t < nr) {
+        rs = row_ptr[i];
+        re = row_ptr[i + 1];
+    }
+    const int32_t base = row_ptr[r0], end = row_ptr[r0 + nr];
+    const int32_t npairs = (end - (base & ~1) + 1) >> 1;
+    // offsets lie in (-n, n); INT32_MAX stands for "no further offset"
+    int32_t ptr = rs, K = 0, cur = 0;
+    bool over = npairs > SPMV_CAP / 2;
+    for (int round = 0; !over && round <= GOI_KMAX; ++round) {
+        if (round > 0)
+            while (ptr < re && col[ptr] - i <= cur) ++ptr;  // a row's offsets ascend with its columns
+        const int32_t mn = block_min_i32(ptr < re ? col[ptr] - i : INT32_MAX, red);
+        if (mn == INT32_MAX) break;
+        if (round == GOI_KMAX) {
+            over = true;
+            break;
+        }
+        if (t == 0) tab[round] = mn;
+        cur = mn;
+        K = round + 1;
+    }
+    __syncthreads();  // tab complete
+    if (over) K = 0;
+    if (t < nr) {
+        uint32_t m = 0;
+        if (K > 0) {
+            int32_t j = 0;
+            for (int32_t e = rs; e < re; ++e) {
+                const int32_t o = col[e] - i;
+                while (j < K && tab[j] != o) ++j;  // every offset of the row is in tab
+                if (j < K) m |= 1u << j;
+            }
+        }
+        goi_mask[i] = (uint16_t)m;
+    }
+    if (t == 0) goi_k[g] = K;
+    if (t < GOI_KMAX) goi_off[(int64_t)g * GOI_KMAX + t] = t < K ? tab[t] : 0;
+}
+
+// out[g] = k of group g, out[ng + g] = row_ptr[g * SPMV_BLOCK], out[2 ng] = row_ptr[n]
+__global__ void goi_summary(int32_t n, int32_t ng, const int32_t* __restrict__ row_ptr,
+                            const int32_t* __restrict__ goi_k, int32_t* __restrict__ out) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < ng) {
+        out[g] = goi_k[g];
+        out[ng + g] = row_ptr[g * SPMV_BLOCK];
+    }
+    if (g == 0) out[2 * (int64_t)ng] = row_ptr[n];
+}
+
+// Build the coded index and count what it covers (n_groups, coded_groups,
+// coded_rows, coded_nnz).
+int goi_build(rp_plan* p, hipStream_t s) {
+    const int64_t n = p->n_rows;
+    const int64_t ng = (n + SPMV_BLOCK - 1) / SPMV_BLOCK;
+    p->n_groups = ng;
+    p->coded_groups = p->coded_rows = p->coded_nnz = 0;
+    RP_HIP_TRY(hipMalloc(&p->d_goi_k, sizeof(int32_t) * (ng > 0 ? ng : 1)));
+    RP_HIP_TRY(hipMalloc(&p->d_goi_off, sizeof(int32_t) * GOI_KMAX * (ng > 0 ? ng : 1)));
+    RP_HIP_TRY(hipMalloc(&p->d_goi_mask, sizeof(uint16_t) * (n > 0 ? n : 1)));
+    if (ng == 0) return RP_OK;
+    hipLaunchKernelGGL(goi_encode, dim3((uint32_t)ng), dim3(SPMV_BLOCK), 0, s, (int32_t)n, p->d_row_ptr,
+                       p->d_col, p->d_goi_k, p->d_goi_off, p->d_goi_mask);
+    RP_HIP_TRY(hipGetLastError());
+    // per group: k and the first entry (row_ptr at every SPMV_BLOCK-th row),
+    // gathered on the device and copied back in one piece
+    int32_t* d_sum = nullptr;
+    RP_HIP_TRY(hipMalloc(&d_sum, sizeof(int32_t) * (2 * ng + 1)));
+    std::vector<int32_t> h(2 * ng + 1);
+    hipLaunchKernelGGL(goi_summary, dim3((uint32_t)((ng + 255) / 256)), dim3(256), 0, s, (int32_t)n, (int32_t)ng,
+                       p->d_row_ptr, p->d_goi_k, d_sum);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d_sum, sizeof(int32_t) * (2 * ng + 1), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_sum);
+    RP_HIP_TRY(e);
+    const int32_t* k = h.data();
+    const int32_t* start = h.data() + ng;
+    for (int64_t g = 0; g < ng; ++g) {
+        if (k[g] <= 0) continue;
+        p->coded_groups += 1;
+        p->coded_rows += std::min<int64_t>(SPMV_BLOCK, n - g * SPMV_BLOCK);
+        p->coded_nnz += start[g + 1] - start[g];
+    }
+    return RP_OK;
+}
+
+}  // namespace
+
 int plan_build(rp_plan* p, const rp_rank_desc* share) {
     const int32_t A = p->alpha;
     hipStream_t s = nullptr;
@@ -432,7 +551,8 @@ int plan_build(rp_plan* p, const rp_rank_desc* share) {
     p->nnz = nnz;
     p->nnz_nl = nnz_nl;
 
-    RP_HIP_TRY(hipMalloc(&p->d_col, sizeof(int32_t) * (nnz > 0 ? nnz : 1)));
+    RP_HIP_TRY(hipMalloc(&p->d_col, sizeof(int32_t) * ((size_t)nnz + SPMV_PAD)));
+    RP_HIP_TRY(hipMemsetAsync(p->d_col + nnz, 0, sizeof(int32_t) * SPMV_PAD, s));
     RP_HIP_TRY(hipMalloc(&p->d_perm_inv, sizeof(int32_t) * (p->n_slots > 0 ? p->n_slots : 1)));
     RP_HIP_TRY(hipMalloc(&p->d_perm, sizeof(int32_t) * (p->n_slots > 0 ? p->n_slots : 1)));
     RP_HIP_TRY(hipMalloc(&p->d_nl_col, sizeof(int64_t) * (nnz_nl > 0 ? nnz_nl : 1)));
@@ -468,7 +588,7 @@ int plan_build(rp_plan* p, const rp_rank_desc* share) {
                   (flags & FLAG_MESH_UNPAIRED) ? "an interface coupling has no partner" : "");
         return RP_ERR_MESH;
     }
-    return RP_OK;
+    return goi_build(p, s);
 }
 
 }  // namespace rp

@@ -82,6 +82,8 @@ struct CgState {
 constexpr int SPMV_BLOCK = 256;               // rows per SpMV block = threads
 constexpr int SPMV_UNROLL = 8;                // staged products per thread
 constexpr int SPMV_CAP = SPMV_UNROLL * SPMV_BLOCK;
+constexpr int SPMV_PAD = 2;                   // zeroed col / val elements past the end (pair loads)
+constexpr int GOI_KMAX = 16;                  // offsets per offset-coded SpMV group (mask width)
 constexpr int VEC_BLOCK = 256;                // elementwise kernels
 constexpr int N_XCD = 8;                      // MI355X: 8 accelerator dies
 
@@ -152,6 +154,13 @@ struct rp_plan {
     rp::CgState<double>* h_st_outer = nullptr;
     uint32_t* d_flags = nullptr;     // [2] error bits, asymmetry flag
     uint32_t* h_flags = nullptr;     // pinned mirror
+
+    // offset-coded SpMV index (see spmv.hpp), built with the pattern
+    int32_t* d_goi_k = nullptr;      // [groups] offsets per group, 0 = CSR group
+    int32_t* d_goi_off = nullptr;    // [groups * GOI_KMAX]
+    uint16_t* d_goi_mask = nullptr;  // [n_rows]
+    int32_t goi_on = 1;              // the kernels use the coded groups
+    int64_t n_groups = 0, coded_groups = 0, coded_rows = 0, coded_nnz = 0;
 
     // x windows of the SpMV (see spmv.hpp): -1 none, 0 diagonal, 1..2 +-d pairs;
     // xw_mode is what the kernels use: xw_found when enabled, else -1

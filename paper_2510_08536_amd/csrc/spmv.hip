@@ -5,16 +5,16 @@ namespace rp {
 
 template <typename T, int NW>
 __global__ void __launch_bounds__(SPMV_BLOCK)
-spmv_kernel(int32_t n_rows, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-            const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y, XWin w) {
-    __shared__ T lds[SPMV_CAP];
+spmv_kernel(int32_t n_rows, SpmvIdx ix, const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y,
+            XWin w) {
+    __shared__ __align__(16) T lds[SPMV_CAP];
     __shared__ T xs[XWinSize<NW>::value];
     const GroupRange gr = block_groups(n_rows);
     for (int32_t g = gr.g0; g < gr.n_groups; g += gr.step) {
         const int32_t r0 = g * SPMV_BLOCK;
         const int32_t nr = min(SPMV_BLOCK, n_rows - r0);
-        const T s = spmv_group_row<T, NW>(row_ptr, col, val, x, n_rows, r0, nr, w, xs, lds);
-        if ((int32_t)threadIdx.x < nr) y[r0 + threadIdx.x] = s;
+        const GroupRow<T> gr_ = spmv_group_row<T, NW>(ix, val, x, n_rows, g, nr, w, xs, lds);
+        if ((int32_t)threadIdx.x < nr) y[r0 + threadIdx.x] = gr_.s;
     }
 }
 
@@ -24,7 +24,7 @@ int launch_spmv(rp_plan* p, const T* val, const T* x, T* y, hipStream_t s) {
     const XWin w{{p->xw_d[0], p->xw_d[1]}};
 #define RP_LAUNCH(NW)                                                                                    \
     hipLaunchKernelGGL((spmv_kernel<T, NW>), dim3(spmv_grid(p->n_rows)), dim3(SPMV_BLOCK), 0, s,        \
-                       (int32_t)p->n_rows, p->d_row_ptr, p->d_col, val, x, y, w)
+                       (int32_t)p->n_rows, spmv_idx(p), val, x, y, w)
     RP_DISPATCH_NW(p->xw_mode, RP_LAUNCH);
 #undef RP_LAUNCH
     RP_HIP_TRY(hipGetLastError());

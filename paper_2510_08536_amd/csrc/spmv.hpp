@@ -1,6 +1,24 @@
 // CSR SpMV over one group of SPMV_BLOCK consecutive rows per workgroup.
 //
-// Matrix stream: the group's nonzeros are one contiguous stretch of val/col.
+// Two index forms, chosen per group when the plan is built:
+//
+// * offset-coded groups: a finite-volume stencil in a rank's natural cell
+//   order couples each row i to i + o for a handful of offsets o (0, +-1,
+//   +-nx, +-nx*ny, plus the jumps across processor interfaces).  When the
+//   rows of a group use at most GOI_KMAX distinct offsets, the group keeps
+//   its CSR values but replaces the column array by one ascending offset
+//   table for the group and one bit mask per row (bit j: the row has column
+//   i + off[j]).  Column order equals offset order, so the values stay in
+//   CSR order.  The SpMV then reads no column indices: the x addresses come
+//   straight from the row number, the table and the mask, so the x loads do
+//   not wait for a load of col, and 4 bytes per entry less cross HBM.
+// * plain CSR groups (everything else: scrambled numberings, rows with many
+//   distinct offsets), described below.
+//
+// Both forms form every product and every row sum exactly as the serial
+// definition does, so results are bit-identical whichever form runs.
+//
+// Matrix stream (CSR groups): the group's nonzeros are one contiguous stretch of val/col.
 // The block reads it with coalesced non-temporal loads of aligned pairs (two
 // values / two column ids per lane), multiplies, parks each product in LDS,
 // and every thread then sums its own row's products in column order.  Each
@@ -39,6 +57,27 @@ struct XWinSize {
     static constexpr int value = NW < 0 ? 1 : XW_DIAG + 2 * NW * SPMV_BLOCK;
 };
 
+// Index arrays of the fused local block.  goi_k == nullptr: CSR everywhere.
+struct SpmvIdx {
+    const int32_t* row_ptr;    // [n+1]
+    const int32_t* col;        // [nnz + SPMV_PAD]
+    const int32_t* goi_k;      // [groups] offsets of a coded group, 0 = CSR group
+    const int32_t* goi_off;    // [groups * GOI_KMAX] ascending col - row
+    const uint16_t* goi_mask;  // [n] bit j: the row has column row + off[j]
+};
+
+// the index the kernels use for plan p
+inline SpmvIdx spmv_idx(const rp_plan* p) {
+    const bool coded = p->goi_on && p->coded_groups > 0;
+    return SpmvIdx{p->d_row_ptr, p->d_col, coded ? p->d_goi_k : nullptr, p->d_goi_off, p->d_goi_mask};
+}
+
+template <typename T>
+struct GroupRow {
+    T s;         // row sum of the thread's row
+    bool coded;  // the group ran offset-coded (no x windows staged)
+};
+
 template <typename T>
 __device__ __forceinline__ T nt_load(const T* p) {
     return __builtin_nontemporal_load(p);
@@ -73,11 +112,12 @@ __device__ __forceinline__ T x_at(int32_t c, int32_t r0, const XWin& w, const T*
     return x[c];
 }
 
-// Row sum for row r0 + threadIdx.x (0 for threads past the group, nr rows).
-// xs: XWinSize<NW> elements of LDS, lds: SPMV_CAP elements.  On return
-// (NW >= 0) xs[XW_HALF + t] holds x of the thread's own row.
+// CSR group: row sum for row r0 + threadIdx.x (0 for threads past the
+// group, nr rows).  xs: XWinSize<NW> elements of LDS, lds: SPMV_CAP
+// elements.  On return (NW >= 0) xs[XW_HALF + t] holds x of the thread's
+// own row.
 template <typename T, int NW>
-__device__ __forceinline__ T spmv_group_row(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+__device__ __forceinline__ T spmv_group_csr(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                            const T* __restrict__ val, const T* __restrict__ x, int32_t n,
                                            int32_t r0, int32_t nr, const XWin& w, T* xs, T* lds) {
 #pragma clang fp contract(off)
@@ -109,31 +149,25 @@ __device__ __forceinline__ T spmv_group_row(const int32_t* __restrict__ row_ptr,
     constexpr int U = SPMV_PAIRS / SPMV_BLOCK;
     IdxPair c[U];
     VP v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        c[u] = IdxPair{0, 0};
-        v[u] = VP{T(0), T(0)};
-    }
-    if (staged) {
+    // Every lane loads a whole aligned pair; lanes past the stretch re-read
+    // its last pair.  The loads thus carry no branch, and all of a thread's
+    // loads are in flight together (a branch per load made the compiler wait
+    // for each one before issuing the next).  The pair that straddles `end`
+    // may touch one element past nnz: col and val hold SPMV_PAD zeroed
+    // elements there, so the spare column is a valid index.  Entries outside
+    // [base, end) are loaded but never used.
+    {
+        const int32_t last = npairs > 0 ? npairs - 1 : 0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int32_t k = t + u * SPMV_BLOCK;
-            if (k < npairs) {
-                if (2 * k + 2 <= end - al) {  // both entries inside [al, end): one 8/16-byte load
-                    c[u] = nt_load(reinterpret_cast<const IdxPair*>(col + al) + k);
-                    v[u] = nt_load(reinterpret_cast<const VP*>(val + al) + k);
-                } else {                       // a lone last entry
-                    c[u].x = col[al + 2 * k];
-                    v[u].x = val[al + 2 * k];
-                    c[u].y = 0;
-                    v[u].y = T(0);
-                }
-            }
+            const int32_t k = min(t + u * SPMV_BLOCK, last);
+            c[u] = nt_load(reinterpret_cast<const IdxPair*>(col + al) + k);
+            v[u] = nt_load(reinterpret_cast<const VP*>(val + al) + k);
         }
     }
     if (NW < 0 && staged) {
         // direct x: issue all gathers before any product so they are in
-        // flight together (lanes without entries hold column 0)
+        // flight together (every lane holds valid columns, see above)
         T gx[2 * U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -172,10 +206,76 @@ __device__ __forceinline__ T spmv_group_row(const int32_t* __restrict__ row_ptr,
     return s;
 }
 
-// x of row i = r0 + threadIdx.x after spmv_group_row (from the diagonal window)
+// Offset-coded group g (K offsets): row sum for row r0 + threadIdx.x.
+// lds: SPMV_CAP elements, 16-byte aligned; the group's stretch of values
+// holds at most SPMV_PAIRS aligned pairs (checked when the plan is built).
+template <typename T>
+__device__ __forceinline__ T spmv_group_coded(const SpmvIdx& ix, const T* __restrict__ val,
+                                             const T* __restrict__ x, int32_t g, int32_t K, int32_t r0,
+                                             int32_t nr, T* lds) {
+#pragma clang fp contract(off)
+    typedef typename Pair<T>::type VP;
+    __shared__ int32_t wtot[SPMV_BLOCK / 64];
+    const int t = threadIdx.x;
+    int32_t off[GOI_KMAX];
+#pragma unroll
+    for (int j = 0; j < GOI_KMAX; ++j) off[j] = ix.goi_off[(int64_t)g * GOI_KMAX + j];
+    const int32_t base = ix.row_ptr[r0];
+    const int32_t end = ix.row_ptr[r0 + nr];
+    const int32_t al = base & ~1;
+    const int32_t npairs = (end - al + 1) >> 1;
+    const int32_t last = npairs > 0 ? npairs - 1 : 0;
+    const uint32_t m = t < nr ? (uint32_t)ix.goi_mask[r0 + t] : 0u;
+    // the row's first entry: exclusive prefix of the row lengths (popcounts)
+    const int32_t c = __popc(m);
+    const int32_t inc = wave_incl_scan(c);
+    if ((t & 63) == 63) wtot[t >> 6] = inc;
+    // values: whole aligned pairs, branch-free as in spmv_group_csr
+    constexpr int U = SPMV_PAIRS / SPMV_BLOCK;
+    VP v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = nt_load(reinterpret_cast<const VP*>(val + al) + min(t + u * SPMV_BLOCK, last));
+    // x of every present entry, all issued before the first use
+    T gx[GOI_KMAX];
+#pragma unroll
+    for (int j = 0; j < GOI_KMAX; ++j) gx[j] = (j < K && ((m >> j) & 1u)) ? x[r0 + t + off[j]] : T(0);
+    __syncthreads();  // previous group's LDS reads done; wtot complete
+    int32_t pos = inc - c + (base - al);
+    for (int q = 0; q < (t >> 6); ++q) pos += wtot[q];
+    // pairs land pair-aligned (lanes past the stretch rewrite the last pair
+    // with the same data)
+    VP* lds2 = reinterpret_cast<VP*>(lds);
+#pragma unroll
+    for (int u = 0; u < U; ++u) lds2[min(t + u * SPMV_BLOCK, last)] = v[u];
+    __syncthreads();
+    T s = T(0);
+#pragma unroll
+    for (int j = 0; j < GOI_KMAX; ++j)
+        if (j < K && ((m >> j) & 1u)) {
+            s += lds[pos] * gx[j];
+            ++pos;
+        }
+    return s;
+}
+
+// Row sum of row g * SPMV_BLOCK + threadIdx.x in the form chosen for group g.
 template <typename T, int NW>
-__device__ __forceinline__ T own_x(int32_t i, const T* xs, const T* __restrict__ x) {
-    if (NW >= 0) return xs[XW_HALF + threadIdx.x];
+__device__ __forceinline__ GroupRow<T> spmv_group_row(const SpmvIdx& ix, const T* __restrict__ val,
+                                                     const T* __restrict__ x, int32_t n, int32_t g, int32_t nr,
+                                                     const XWin& w, T* xs, T* lds) {
+    const int32_t r0 = g * SPMV_BLOCK;
+    if (ix.goi_k != nullptr) {
+        const int32_t K = ix.goi_k[g];
+        if (K > 0) return GroupRow<T>{spmv_group_coded<T>(ix, val, x, g, K, r0, nr, lds), true};
+    }
+    return GroupRow<T>{spmv_group_csr<T, NW>(ix.row_ptr, ix.col, val, x, n, r0, nr, w, xs, lds), false};
+}
+
+// x of row i = r0 + threadIdx.x after spmv_group_row (from the diagonal
+// window when the group ran in CSR form with windows)
+template <typename T, int NW>
+__device__ __forceinline__ T own_x(int32_t i, bool coded, const T* xs, const T* __restrict__ x) {
+    if (NW >= 0 && !coded) return xs[XW_HALF + threadIdx.x];
     return x[i];
 }
 

@@ -43,7 +43,7 @@ STATUS_NAMES = {0: "RP_OK", 1: "RP_NOT_CONVERGED", -1: "RP_ERR_ARG", -2: "RP_ERR
                 -6: "RP_ERR_BREAKDOWN", -7: "RP_ERR_VALUE"}
 
 EXPORTED = ["rp_plan_create", "rp_plan_destroy", "rp_plan_sizes", "rp_plan_get_csr", "rp_plan_get_values",
-            "rp_plan_spmv_windows", "rp_plan_set_spmv_windows",
+            "rp_plan_spmv_windows", "rp_plan_set_spmv_windows", "rp_plan_spmv_format", "rp_plan_set_spmv_format",
             "rp_update_values", "rp_update_values_slots", "rp_spmv", "rp_solve", "rp_solve_opts_default",
             "rp_value_grad", "rp_sync", "rp_last_error", "rp_plan_set_timing", "rp_plan_kernel_stats"]
 
@@ -70,6 +70,15 @@ class rp_solve_info(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class rp_spmv_format(C.Structure):
+    _fields_ = [("enabled", C.c_int32), ("reserved", C.c_int32), ("n_groups", C.c_int64),
+                ("coded_groups", C.c_int64), ("coded_rows", C.c_int64), ("coded_nnz", C.c_int64),
+                ("bytes64", C.c_int64), ("bytes32", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 _P = C.c_void_p
 _PP = C.POINTER(C.c_void_p)
 _i32p = C.POINTER(C.c_int32)
@@ -84,6 +93,8 @@ _sig = {
     "rp_plan_get_values": (C.c_int, [_P, _P, _P, _P, _P]),
     "rp_plan_spmv_windows": (C.c_int, [_P, _i32p, _i32p, _i32p]),
     "rp_plan_set_spmv_windows": (C.c_int, [_P, C.c_int32]),
+    "rp_plan_spmv_format": (C.c_int, [_P, C.POINTER(rp_spmv_format)]),
+    "rp_plan_set_spmv_format": (C.c_int, [_P, C.c_int32]),
     "rp_update_values": (C.c_int, [_P, _PP, _PP, _PP, _PP, _P]),
     "rp_update_values_slots": (C.c_int, [_P, _P, _P]),
     "rp_spmv": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
@@ -219,6 +230,16 @@ class Plan:
 
     def set_spmv_windows(self, enable: bool):
         _check(rp_plan_set_spmv_windows(self._h, int(bool(enable))), "rp_plan_set_spmv_windows")
+
+    def spmv_format(self) -> dict:
+        """Column-index form of the SpMV: coded groups, rows, entries and the
+        algorithmic bytes of one FP64 / FP32 y = A x in the form in use."""
+        f = rp_spmv_format()
+        _check(rp_plan_spmv_format(self._h, C.byref(f)), "rp_plan_spmv_format")
+        return f.as_dict()
+
+    def set_spmv_format(self, coded: bool):
+        _check(rp_plan_set_spmv_format(self._h, int(bool(coded))), "rp_plan_set_spmv_format")
 
     def get_csr(self):
         row_ptr = np.zeros(self.n_rows + 1, np.int32)

@@ -61,6 +61,7 @@ int main(void) {
   printf("rp_rank_desc %zu\n", sizeof(rp_rank_desc));
   printf("rp_solve_opts %zu\n", sizeof(rp_solve_opts));
   printf("rp_solve_info %zu\n", sizeof(rp_solve_info));
+  printf("rp_spmv_format %zu\n", sizeof(rp_spmv_format));
   F(rp_rank_desc, n_cells); F(rp_rank_desc, n_faces); F(rp_rank_desc, owner); F(rp_rank_desc, neighbour);
   F(rp_rank_desc, n_iface); F(rp_rank_desc, iface_cell); F(rp_rank_desc, iface_nbr_rank);
   F(rp_rank_desc, iface_nbr_cell);
@@ -70,6 +71,9 @@ int main(void) {
   F(rp_solve_opts, max_restarts);
   F(rp_solve_info, status); F(rp_solve_info, iters); F(rp_solve_info, outer_iters); F(rp_solve_info, restarts);
   F(rp_solve_info, rel_res);
+  F(rp_spmv_format, enabled); F(rp_spmv_format, reserved); F(rp_spmv_format, n_groups);
+  F(rp_spmv_format, coded_groups); F(rp_spmv_format, coded_rows); F(rp_spmv_format, coded_nnz);
+  F(rp_spmv_format, bytes64); F(rp_spmv_format, bytes32);
   return 0;
 }
 """
@@ -81,7 +85,7 @@ int main(void) {
         out = subprocess.check_output([exe], text=True).split("\n")
     got = dict(line.rsplit(" ", 1) for line in out if line)
     for name, cls in (("rp_rank_desc", rp.rp_rank_desc), ("rp_solve_opts", rp.rp_solve_opts),
-                      ("rp_solve_info", rp.rp_solve_info)):
+                      ("rp_solve_info", rp.rp_solve_info), ("rp_spmv_format", rp.rp_spmv_format)):
         assert int(got[name]) == ctypes.sizeof(cls), name
         for field, _ in cls._fields_:
             assert int(got[f"{name}.{field}"]) == getattr(cls, field).offset, (name, field)

@@ -28,6 +28,8 @@ CASES = {
     "single_rank": ((7, 6, 5), ("blocks", 1, 1, 1), dict(kappa=(1e-2, 1.0), scramble=True)),
     "two_pairs": ((80, 3, 5), ("blocks", 1, 1, 1), dict(kappa=(1e-2, 1.0))),
     "banded_ragged": ((20, 9, 31), ("blocks", 1, 2, 3), dict(kappa=(1e-2, 1.0))),
+    # oblique cut planes: 10 of 38 row groups offset-coded, the rest CSR
+    "rcb_mixed": ((40, 20, 12), ("rcb", 3), dict(kappa=(1e-2, 1.0))),
 }
 
 
@@ -152,27 +154,98 @@ def test_spmv_window_detection():
     plan.close()
 
 
+def _host_format(row_ptr, col, n):
+    """The SpMV form rule restated on the host: a group of 256 rows is
+    offset-coded iff its entries use at most 16 distinct col - row and its
+    values span at most 1024 aligned pairs."""
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    ng = (n + 255) // 256
+    out = dict(n_groups=ng, coded_groups=0, coded_rows=0, coded_nnz=0)
+    for g in range(ng):
+        r0, r1 = g * 256, min(n, g * 256 + 256)
+        s, e = rp[r0], rp[r1]
+        rows = np.repeat(np.arange(r0, r1), np.diff(rp[r0:r1 + 1]))
+        k = np.unique(np.asarray(col[s:e], dtype=np.int64) - rows).size
+        if 0 < k <= 16 and ((e - (s & ~1) + 1) >> 1) <= 1024:
+            out["coded_groups"] += 1
+            out["coded_rows"] += r1 - r0
+            out["coded_nnz"] += int(e - s)
+    return out
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_spmv_format_coverage_and_bytes(name):
+    """Which groups are offset-coded (integer work: exact), and the bytes
+    reported for one y = A x in each form."""
+    w = _work(name)
+    for first, alpha in _shares(w):
+        m = oracle.merge(w.part.n_cells, first, alpha, share_ranks(w, first, alpha))
+        plan = make_plan(w, first, alpha)
+        f = plan.spmv_format()
+        want = _host_format(m.row_ptr, m.col, m.n_rows)
+        assert f["enabled"] == 1
+        assert {k: f[k] for k in want} == want, (name, first, alpha)
+        n, nnz = m.n_rows, m.nnz_local
+        cg, cr, cn = want["coded_groups"], want["coded_rows"], want["coded_nnz"]
+        for key, sv in (("bytes64", 8), ("bytes32", 4)):
+            coded = cn * sv + 2 * cr + 72 * cg + (nnz - cn) * (sv + 4) + 4 * (n - cr) + 2 * n * sv + 4
+            assert f[key] == coded, (name, key)
+        plan.set_spmv_format(False)
+        f = plan.spmv_format()
+        assert f["enabled"] == 0
+        assert f["bytes64"] == 12 * nnz + 20 * n + 4 and f["bytes32"] == 8 * nnz + 12 * n + 4
+        plan.close()
+
+
+SPMV_MODES = ["coded", "csr", "csr_windows", "coded_windows"]
+
+
+def _set_mode(plan, mode):
+    plan.set_spmv_format(mode.startswith("coded"))
+    plan.set_spmv_windows(mode.endswith("windows"))
+
+
 @pytest.mark.parametrize("name", ["ragged_rcb7", "slabs_c1like", "stretched_rcb", "one_cell_per_rank",
-                                  "single_rank", "chain8_4", "two_pairs", "banded_ragged"])
-@pytest.mark.parametrize("windows", [False, True])
-def test_spmv_fp64_bit_exact(name, windows):
+                                  "single_rank", "chain8_4", "two_pairs", "banded_ragged", "rcb_mixed"])
+@pytest.mark.parametrize("mode", SPMV_MODES)
+def test_spmv_fp64_bit_exact(name, mode):
     w = _work(name, seed=7)
     m, buf, val64, val32, *_ = oracle_system(w)
     plan = make_plan(w)
-    assert not plan.spmv_windows_enabled()
-    plan.set_spmv_windows(windows)
-    assert plan.spmv_windows_enabled() == (windows and plan.spmv_windows()[0] >= 0)
+    assert not plan.spmv_windows_enabled() and plan.spmv_format()["enabled"] == 1
+    _set_mode(plan, mode)
+    assert plan.spmv_windows_enabled() == (mode.endswith("windows") and plan.spmv_windows()[0] >= 0)
     update(plan, share_values(w))
     rng = np.random.default_rng(2)
     for x in (rng.uniform(-1, 1, m.n_rows), rng.standard_normal(m.n_rows) * 1e3, np.zeros(m.n_rows)):
         y = plan.spmv(dev_tensor(x)).cpu().numpy()
-        assert_bits_equal(y, oracle.spmv(m, val64, x), f"{name} spmv64 windows={windows}")
+        assert_bits_equal(y, oracle.spmv(m, val64, x), f"{name} spmv64 {mode}")
     plan.close()
 
 
-@pytest.mark.parametrize("name", ["ragged_rcb7", "slabs_c1like", "two_pairs", "banded_ragged"])
-@pytest.mark.parametrize("windows", [False, True])
-def test_spmv_fp32_error_bound(name, windows):
+def test_spmv_fp32_same_bits_in_both_forms():
+    """The FP32 SpMV forms every product and row sum in the same order in
+    both index forms, so their results agree bit for bit."""
+    torch = torch_mod()
+    for name in ("slabs_c1like", "rcb_mixed", "banded_ragged"):
+        w = _work(name, seed=9)
+        m, *_ = oracle_system(w)
+        plan = make_plan(w)
+        update(plan, share_values(w))
+        x32 = dev_tensor(np.random.default_rng(4).uniform(-1, 1, m.n_rows).astype(np.float32))
+        ys = []
+        for mode in SPMV_MODES:
+            _set_mode(plan, mode)
+            ys.append(plan.spmv(x32).cpu().numpy())
+        for mode, y in zip(SPMV_MODES[1:], ys[1:]):
+            assert_bits_equal(y, ys[0], f"{name} spmv32 {mode} vs coded")
+        plan.close()
+    del torch
+
+
+@pytest.mark.parametrize("name", ["ragged_rcb7", "slabs_c1like", "two_pairs", "banded_ragged", "rcb_mixed"])
+@pytest.mark.parametrize("mode", SPMV_MODES)
+def test_spmv_fp32_error_bound(name, mode):
     """FP32 SpMV: each row sums k products with one rounding each, so
     |y32 - y| <= gamma_{k+1} * sum |a_ij x_j| with gamma_m = m u / (1 - m u),
     u = 2^-24, against the exact (FP64) product of the same FP32 inputs."""
@@ -180,7 +253,7 @@ def test_spmv_fp32_error_bound(name, windows):
     w = _work(name, seed=9)
     m, buf, val64, val32, *_ = oracle_system(w)
     plan = make_plan(w)
-    plan.set_spmv_windows(windows)
+    _set_mode(plan, mode)
     update(plan, share_values(w))
     x32 = np.random.default_rng(4).uniform(-1, 1, m.n_rows).astype(np.float32)
     y = plan.spmv(dev_tensor(x32)).cpu().numpy().astype(np.float64)

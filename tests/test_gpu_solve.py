@@ -22,6 +22,8 @@ CASES = {
     "stretched": lambda: synth.small((12, 12, 20), ("rcb", 6), kappa=(1e-3, 1.0), seed=22, scramble=True,
                                      stretch=100.0),
     "chain": lambda: synth.small((300, 1, 1), ("blocks", 5, 1, 1), seed=23, walls=(True, False, False)),
+    # oblique cut planes: some row groups offset-coded, the rest CSR
+    "rcb_mixed": lambda: synth.small((40, 20, 12), ("rcb", 3), kappa=(1e-2, 1.0), seed=24),
 }
 
 
@@ -115,6 +117,25 @@ def test_windows_do_not_change_solves():
         plan.set_spmv_windows(True)
         x1, i1 = plan.solve(b, precision=prec)
         assert i0["iters"] == i1["iters"] and torch_mod().equal(x0, x1), prec
+    plan.close()
+
+
+@pytest.mark.parametrize("name", ["c1", "rcb_mixed", "ragged_rcb7"])
+def test_spmv_form_does_not_change_solves(name):
+    """The offset-coded and the CSR index form give the same products and row
+    sums, so FP64 and mixed solves are bit-identical in either form (and with
+    the x windows of the CSR groups on)."""
+    w, m, val64, plan = _setup(name)
+    b = dev_tensor(w.rhs())
+    for prec in ("fp64", "mixed"):
+        runs = []
+        for coded, windows in ((True, False), (False, False), (False, True), (True, True)):
+            plan.set_spmv_format(coded)
+            plan.set_spmv_windows(windows)
+            x, info = plan.solve(b, precision=prec)
+            runs.append((x, info["iters"], info["outer_iters"]))
+        for x, it, outer in runs[1:]:
+            assert (it, outer) == runs[0][1:] and torch_mod().equal(x, runs[0][0]), (name, prec)
     plan.close()
 
 
