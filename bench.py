@@ -208,8 +208,8 @@ def main():
     fmt = plan.spmv_format()
     spmv64_bytes = fmt["bytes64"]
     spmv32_bytes = fmt["bytes32"]
-    iter64_bytes = spmv64_bytes + 88 * n     # + x, r, p, q, M^-1 / x, r out (K2) + r, M^-1, p / p out (K3)
-    iter32_bytes = spmv32_bytes + 44 * n
+    iter64_bytes = spmv64_bytes + 80 * n     # + r, q, M^-1 / r out (K2) + x, p, r, M^-1 / x, p out (K3)
+    iter32_bytes = spmv32_bytes + 40 * n
     csr64_bytes = 12 * nnz + 20 * n + 4
     spmv_avg_ms = ms_spmv / max(n_spmv, 1)
     spmv_gbs = spmv64_bytes / (spmv_avg_ms * 1e-3) / 1e9

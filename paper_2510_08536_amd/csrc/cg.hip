@@ -3,9 +3,10 @@
 //
 // Iteration k is three kernels; all scalars stay on the device:
 //   K1  q = A p                      partials of (p, q)
-//   K2  alpha = rz_k / (p, q)        x += alpha p, r -= alpha q;
+//   K2  alpha = rz_k / (p, q)        r -= alpha q;
 //                                    partials of (r, M^-1 r) and (r, r)
-//   K3  stop tests, beta = rz_{k+1} / rz_k, p = M^-1 r + beta p
+//   K3  x += alpha p; stop tests, beta = rz_{k+1} / rz_k, p = M^-1 r + beta p
+// (x moves in K3, which reads p anyway: one pass over p less per iteration)
 // Each kernel starts by adding up the previous kernel's per-block partials
 // (every block the same sum, in index order), so reductions need no atomics,
 // no fences and no extra launches, and reruns are bit-identical.  The
@@ -167,13 +168,12 @@ cg_spmv_pq(int32_t n, SpmvIdx ix, const T* __restrict__ val, const T* __restrict
     if (threadIdx.x == 0) part[PART_A + xcd_block()] = b;
 }
 
-// K2: alpha = rz_k / (p, q); x += alpha p, r -= alpha q; partials of
-// (r, M^-1 r) -> PART_RZ and (r, r) -> PART_RR
+// K2: alpha = rz_k / (p, q); r -= alpha q; partials of (r, M^-1 r) ->
+// PART_RZ and (r, r) -> PART_RR.  x moves in K3, which reads p anyway.
 template <typename T>
 __global__ void __launch_bounds__(VEC_BLOCK)
-cg_update_xr(int32_t n, int32_t k, int32_t g_spmv, T* __restrict__ x, T* __restrict__ r,
-             const T* __restrict__ p, const T* __restrict__ q, const T* __restrict__ dinv,
-             T* __restrict__ part, CgState<T>* st) {
+cg_update_r(int32_t n, int32_t k, int32_t g_spmv, T* __restrict__ r, const T* __restrict__ q,
+            const T* __restrict__ dinv, T* __restrict__ part, CgState<T>* st) {
 #pragma clang fp contract(off)
     if (st->done != CG_RUNNING) return;
     __shared__ T red[VEC_BLOCK / 64];
@@ -189,9 +189,7 @@ cg_update_xr(int32_t n, int32_t k, int32_t g_spmv, T* __restrict__ x, T* __restr
     const T a = st->rz[k & 3] / pq;
     T prz = T(0), prr = T(0);
     for (int32_t i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK) {
-        const T xi = x[i] + a * p[i];
         const T ri = r[i] - a * q[i];
-        x[i] = xi;
         r[i] = ri;
         const T zi = dinv[i] * ri;
         prz += ri * zi;
@@ -209,13 +207,16 @@ cg_update_xr(int32_t n, int32_t k, int32_t g_spmv, T* __restrict__ x, T* __restr
     }
 }
 
-// K3: stop tests on (r, r), beta = rz_{k+1} / rz_k, p = M^-1 r + beta p.
-// resume: continue after the residual was replaced (partials from cg_rz_rr),
-// skipping the stop tests.
+// K3: x += alpha p (K2's alpha); stop tests on (r, r); unless stopping,
+// beta = rz_{k+1} / rz_k and p = M^-1 r + beta p.  x uses the old p, exactly
+// as if K2 had moved it.  resume: continue after the residual was replaced
+// (partials from cg_rz_rr): x already holds this iteration's step, the stop
+// tests are skipped.
 template <typename T>
 __global__ void __launch_bounds__(VEC_BLOCK)
-cg_update_p(int32_t n, int32_t k, int32_t g_vec, int32_t resume, const T* __restrict__ r,
-            const T* __restrict__ dinv, T* __restrict__ p, const T* __restrict__ part, CgState<T>* st) {
+cg_update_xp(int32_t n, int32_t k, int32_t g_vec, int32_t resume, const T* __restrict__ r,
+             const T* __restrict__ dinv, T* __restrict__ x, T* __restrict__ p, const T* __restrict__ part,
+             CgState<T>* st) {
 #pragma clang fp contract(off)
     if (!resume && st->done != CG_RUNNING) return;
     __shared__ T red[VEC_BLOCK / 64];
@@ -226,7 +227,11 @@ cg_update_p(int32_t n, int32_t k, int32_t g_vec, int32_t resume, const T* __rest
     if (!resume && rr <= st->thresh) stop = CG_CONVERGED;
     else if (!(rz > T(0)) || !isfinite(rz)) stop = CG_BREAKDOWN;
     else if (!resume && rr <= st->pause_thresh) stop = CG_PAUSED;
+    const T a = st->alpha;
+    const int32_t i0 = blockIdx.x * VEC_BLOCK + threadIdx.x, di = gridDim.x * VEC_BLOCK;
     if (stop != CG_RUNNING) {
+        if (!resume)
+            for (int32_t i = i0; i < n; i += di) x[i] = x[i] + a * p[i];
         if (lead) {
             st->rr = rr;
             st->iter = k + 1;
@@ -235,8 +240,15 @@ cg_update_p(int32_t n, int32_t k, int32_t g_vec, int32_t resume, const T* __rest
         return;
     }
     const T beta = rz / st->rz[k & 3];
-    for (int32_t i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK)
-        p[i] = dinv[i] * r[i] + beta * p[i];
+    if (resume) {
+        for (int32_t i = i0; i < n; i += di) p[i] = dinv[i] * r[i] + beta * p[i];
+    } else {
+        for (int32_t i = i0; i < n; i += di) {
+            const T pi = p[i];
+            x[i] = x[i] + a * pi;
+            p[i] = dinv[i] * r[i] + beta * pi;
+        }
+    }
     if (lead) {
         st->rz[(k + 1) & 3] = rz;
         st->rr = rr;
@@ -343,8 +355,8 @@ template <typename T>
 int launch_resume(Cg<T>& c) {
     const int32_t k = c.h->iter - 1;
     hipLaunchKernelGGL(cg_rz_rr<T>, dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, c.r, c.dinv, c.part);
-    hipLaunchKernelGGL(cg_update_p<T>, dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, k, c.g_vec, 1, c.r, c.dinv,
-                       c.p, c.part, c.st);
+    hipLaunchKernelGGL(cg_update_xp<T>, dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, k, c.g_vec, 1, c.r, c.dinv,
+                       c.x, c.p, c.part, c.st);
     RP_HIP_TRY(hipGetLastError());
     return RP_OK;
 }
@@ -365,9 +377,9 @@ int iterate(Cg<T>& c, int chunk, int32_t max_iter) {
             RP_DISPATCH_NW(c.xw_mode, RP_LAUNCH);
 #undef RP_LAUNCH
             RP_TRY(timing_end(c.plan, c.kernel_id, c.s));
-            hipLaunchKernelGGL(cg_update_xr<T>, gv, bv, 0, c.s, c.n, k, c.g_spmv, c.x, c.r, c.p, c.q, c.dinv,
-                               c.part, c.st);
-            hipLaunchKernelGGL(cg_update_p<T>, gv, bv, 0, c.s, c.n, k, c.g_vec, 0, c.r, c.dinv, c.p, c.part, c.st);
+            hipLaunchKernelGGL(cg_update_r<T>, gv, bv, 0, c.s, c.n, k, c.g_spmv, c.r, c.q, c.dinv, c.part, c.st);
+            hipLaunchKernelGGL(cg_update_xp<T>, gv, bv, 0, c.s, c.n, k, c.g_vec, 0, c.r, c.dinv, c.x, c.p, c.part,
+                               c.st);
         }
         RP_HIP_TRY(hipGetLastError());
         RP_TRY(read_state(c));
