@@ -98,7 +98,7 @@ int dalloc(T** q, int64_t count) {
 int alloc_values(rp_plan* p) {
     const int64_t n = p->n_rows, ns = p->n_slots;
     RP_TRY(dalloc(&p->d_recv, ns));
-    // SpMV pair loads may touch SPMV_PAD elements past the values
+    // SpMV pack loads may touch SPMV_PAD elements past the values
     RP_TRY(dalloc(&p->d_val64, ns + SPMV_PAD));
     RP_TRY(dalloc(&p->d_val32, ns + SPMV_PAD));
     RP_HIP_TRY(hipMemset(p->d_val64 + ns, 0, sizeof(double) * SPMV_PAD));

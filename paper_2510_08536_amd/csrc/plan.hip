@@ -359,7 +359,8 @@ __device__ __forceinline__ int32_t block_min_i32(int32_t v, int32_t* red) {
 // One block per group of SPMV_BLOCK rows (columns already sorted per row).
 // The distinct offsets col - row of the group are found smallest first, one
 // block-wide minimum per offset; a group with more than GOI_KMAX of them, or
-// whose values span more than SPMV_CAP / 2 aligned pairs, stays CSR (k = 0).
+// whose aligned value packs (2 doubles, 4 floats) would not fit SPMV_CAP
+// elements, stays CSR (k = 0).
 __global__ void __launch_bounds__(SPMV_BLOCK)
 goi_encode(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
            int32_t* __restrict__ goi_k, int32_t* __restrict__ goi_off, uint16_t* __restrict__ goi_mask) {
@@ -374,9 +375,10 @@ goi_encode(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __rest
     }
     const int32_t base = row_ptr[r0], end = row_ptr[r0 + nr];
     const int32_t npairs = (end - (base & ~1) + 1) >> 1;
+    const int32_t nquads = (end - (base & ~3) + 3) >> 2;
     // offsets lie in (-n, n); INT32_MAX stands for "no further offset"
     int32_t ptr = rs, K = 0, cur = 0;
-    bool over = npairs > SPMV_CAP / 2;
+    bool over = npairs > SPMV_CAP / 2 || nquads > SPMV_CAP / 4;
     for (int round = 0; !over && round <= GOI_KMAX; ++round) {
         if (round > 0)
             while (ptr < re && col[ptr] - i <= cur) ++ptr;  // a row's offsets ascend with its columns

@@ -82,7 +82,7 @@ struct CgState {
 constexpr int SPMV_BLOCK = 256;               // rows per SpMV block = threads
 constexpr int SPMV_UNROLL = 8;                // staged products per thread
 constexpr int SPMV_CAP = SPMV_UNROLL * SPMV_BLOCK;
-constexpr int SPMV_PAD = 2;                   // zeroed col / val elements past the end (pair loads)
+constexpr int SPMV_PAD = 4;                   // zeroed col / val elements past the end (pack loads)
 constexpr int GOI_KMAX = 16;                  // offsets per offset-coded SpMV group (mask width)
 constexpr int VEC_BLOCK = 256;                // elementwise kernels
 constexpr int N_XCD = 8;                      // MI355X: 8 accelerator dies

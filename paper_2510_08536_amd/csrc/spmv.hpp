@@ -78,6 +78,9 @@ struct GroupRow {
     bool coded;  // the group ran offset-coded (no x windows staged)
 };
 
+// cache-policy bits of the direct-to-LDS loads: non-temporal (streamed once)
+constexpr int SPMV_NT_AUX = 2;
+
 template <typename T>
 __device__ __forceinline__ T nt_load(const T* p) {
     return __builtin_nontemporal_load(p);
@@ -94,6 +97,20 @@ struct Pair<float> {
     typedef float type __attribute__((ext_vector_type(2)));
 };
 typedef int32_t IdxPair __attribute__((ext_vector_type(2)));
+
+// 16-byte packs of values (E entries) for the coded groups' value stream
+template <typename T>
+struct Pack;
+template <>
+struct Pack<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+    static constexpr int E = 2;
+};
+template <>
+struct Pack<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static constexpr int E = 4;
+};
 
 // x[c] from the LDS windows of the group starting at row r0, else from global
 template <typename T, int NW>
@@ -207,14 +224,16 @@ __device__ __forceinline__ T spmv_group_csr(const int32_t* __restrict__ row_ptr,
 }
 
 // Offset-coded group g (K offsets): row sum for row r0 + threadIdx.x.
-// lds: SPMV_CAP elements, 16-byte aligned; the group's stretch of values
-// holds at most SPMV_PAIRS aligned pairs (checked when the plan is built).
+// lds: SPMV_CAP elements, 16-byte aligned.  The group's values are read as
+// aligned 16-byte packs (2 doubles or 4 floats); when the plan is built, a
+// group is coded only if its packs fit SPMV_CAP elements in both precisions.
 template <typename T>
 __device__ __forceinline__ T spmv_group_coded(const SpmvIdx& ix, const T* __restrict__ val,
                                              const T* __restrict__ x, int32_t g, int32_t K, int32_t r0,
                                              int32_t nr, T* lds) {
 #pragma clang fp contract(off)
-    typedef typename Pair<T>::type VP;
+    typedef typename Pack<T>::type VP;
+    constexpr int E = Pack<T>::E;
     __shared__ int32_t wtot[SPMV_BLOCK / 64];
     const int t = threadIdx.x;
     int32_t off[GOI_KMAX];
@@ -222,32 +241,38 @@ __device__ __forceinline__ T spmv_group_coded(const SpmvIdx& ix, const T* __rest
     for (int j = 0; j < GOI_KMAX; ++j) off[j] = ix.goi_off[(int64_t)g * GOI_KMAX + j];
     const int32_t base = ix.row_ptr[r0];
     const int32_t end = ix.row_ptr[r0 + nr];
-    const int32_t al = base & ~1;
-    const int32_t npairs = (end - al + 1) >> 1;
-    const int32_t last = npairs > 0 ? npairs - 1 : 0;
+    const int32_t al = base & ~(E - 1);            // packs start on a multiple of E
+    const int32_t npk = (end - al + E - 1) / E;
+    const int32_t last = npk > 0 ? npk - 1 : 0;
     const uint32_t m = t < nr ? (uint32_t)ix.goi_mask[r0 + t] : 0u;
+    __syncthreads();  // the previous group's LDS reads are done before any load lands there
     // the row's first entry: exclusive prefix of the row lengths (popcounts)
     const int32_t c = __popc(m);
     const int32_t inc = wave_incl_scan(c);
     if ((t & 63) == 63) wtot[t >> 6] = inc;
-    // values: whole aligned pairs, branch-free as in spmv_group_csr
-    constexpr int U = SPMV_PAIRS / SPMV_BLOCK;
-    VP v[U];
+    // values: whole 16-byte packs straight from HBM into LDS.  The load
+    // writes lane-linearly from a wave-uniform base, and pack k of the stretch
+    // lands in LDS slot k.  Lanes past the stretch re-read its last pack into
+    // their own (unused) slot; that pack may reach E - 1 elements past `end`
+    // (SPMV_PAD).
+    constexpr int U = SPMV_CAP / E / SPMV_BLOCK;
+    typedef __attribute__((address_space(3))) void* LdsPtr;
+    const int32_t wave0 = t & ~63;
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = nt_load(reinterpret_cast<const VP*>(val + al) + min(t + u * SPMV_BLOCK, last));
+    for (int u = 0; u < U; ++u)
+        __builtin_amdgcn_global_load_lds((void*)(reinterpret_cast<const VP*>(val + al) + min(t + u * SPMV_BLOCK, last)),
+                                         (LdsPtr)(reinterpret_cast<VP*>(lds) + u * SPMV_BLOCK + wave0), 16, 0,
+                                         SPMV_NT_AUX);
     // x of every present entry, all issued before the first use
     T gx[GOI_KMAX];
 #pragma unroll
     for (int j = 0; j < GOI_KMAX; ++j) gx[j] = (j < K && ((m >> j) & 1u)) ? x[r0 + t + off[j]] : T(0);
-    __syncthreads();  // previous group's LDS reads done; wtot complete
+    // the packs of every wave must be in LDS before any wave reads them: wait
+    // for all of this wave's loads, then the barrier
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
     int32_t pos = inc - c + (base - al);
     for (int q = 0; q < (t >> 6); ++q) pos += wtot[q];
-    // pairs land pair-aligned (lanes past the stretch rewrite the last pair
-    // with the same data)
-    VP* lds2 = reinterpret_cast<VP*>(lds);
-#pragma unroll
-    for (int u = 0; u < U; ++u) lds2[min(t + u * SPMV_BLOCK, last)] = v[u];
-    __syncthreads();
     T s = T(0);
 #pragma unroll
     for (int j = 0; j < GOI_KMAX; ++j)

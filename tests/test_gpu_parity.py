@@ -157,7 +157,7 @@ def test_spmv_window_detection():
 def _host_format(row_ptr, col, n):
     """The SpMV form rule restated on the host: a group of 256 rows is
     offset-coded iff its entries use at most 16 distinct col - row and its
-    values span at most 1024 aligned pairs."""
+    values span at most 1024 aligned pairs and 512 aligned quads."""
     rp = np.asarray(row_ptr, dtype=np.int64)
     ng = (n + 255) // 256
     out = dict(n_groups=ng, coded_groups=0, coded_rows=0, coded_nnz=0)
@@ -166,7 +166,7 @@ def _host_format(row_ptr, col, n):
         s, e = rp[r0], rp[r1]
         rows = np.repeat(np.arange(r0, r1), np.diff(rp[r0:r1 + 1]))
         k = np.unique(np.asarray(col[s:e], dtype=np.int64) - rows).size
-        if 0 < k <= 16 and ((e - (s & ~1) + 1) >> 1) <= 1024:
+        if 0 < k <= 16 and ((e - (s & ~1) + 1) >> 1) <= 1024 and ((e - (s & ~3) + 3) >> 2) <= 512:
             out["coded_groups"] += 1
             out["coded_rows"] += r1 - r0
             out["coded_nnz"] += int(e - s)
