@@ -203,17 +203,21 @@ def main():
     last = recs[-1]
     diff = (torch.linalg.vector_norm(last["x64"] - last["xmx"]) / torch.linalg.vector_norm(last["x64"])).item()
 
-    # algorithmic bytes per unit (each array read once, ideal reuse of x); the
-    # SpMV's depend on its index form (offset-coded groups need no col array)
+    # algorithmic bytes per unit of work (each array read once, ideal reuse of
+    # x): the CSR SpMV moves val + col per entry, row_ptr, x and y; a PCG
+    # iteration adds the vector kernels.  The kernels move less where row
+    # groups are offset-coded (no col array); those bytes are reported beside.
     fmt = plan.spmv_format()
-    spmv64_bytes = fmt["bytes64"]
-    spmv32_bytes = fmt["bytes32"]
-    iter64_bytes = spmv64_bytes + 80 * n     # + r, q, M^-1 / r out (K2) + x, p, r, M^-1 / x, p out (K3)
-    iter32_bytes = spmv32_bytes + 40 * n
-    csr64_bytes = 12 * nnz + 20 * n + 4
+    spmv64_bytes = 12 * nnz + 20 * n + 4
+    spmv32_bytes = 8 * nnz + 12 * n + 4
+    iter64_bytes = 12 * nnz + 108 * n
+    iter32_bytes = 8 * nnz + 56 * n
+    kern64_bytes = fmt["bytes64"]            # what the SpMV kernels read and write in the form in use
+    kern32_bytes = fmt["bytes32"]
     spmv_avg_ms = ms_spmv / max(n_spmv, 1)
+    spmv32_avg_ms = ms_spmv32 / max(n_spmv32, 1)
     spmv_gbs = spmv64_bytes / (spmv_avg_ms * 1e-3) / 1e9
-    spmv32_gbs = spmv32_bytes / (ms_spmv32 / max(n_spmv32, 1) * 1e-3) / 1e9
+    spmv32_gbs = spmv32_bytes / (spmv32_avg_ms * 1e-3) / 1e9
     med = lambda v: float(np.median(v))
 
     out = {
@@ -241,6 +245,7 @@ def main():
                   "rel_diff_vs_fp64_solution": diff,
                   "inner_iter_GBps_alg": round(iter32_bytes * np.median(itmx) / (med(mx) * 1e-3) / 1e9, 1)},
         "adjoint_ms": round(med(adj), 3),
+        "adjoint_iters": int(np.median([r["adj"]["iters"] for r in recs])),
         "update_ms": round(med(upd), 3),
         "update_scatter_ms": round(ms_scat / max(n_scat, 1), 4),
         "update_host_staged_ms": round(update_host_ms, 3),
@@ -249,11 +254,14 @@ def main():
         "spmv32_GBps": round(spmv32_gbs, 1),
         "spmv_format": {"coded_groups": fmt["coded_groups"], "n_groups": fmt["n_groups"],
                         "coded_nnz_frac": round(fmt["coded_nnz"] / max(nnz, 1), 4),
-                        "csr_equiv_GBps": round(csr64_bytes / (spmv_avg_ms * 1e-3) / 1e9, 1)},
-        "roofline": {"bound": "hbm", "kernel": "cg_spmv_pq<double> (FP64 SpMV, offset-coded row groups, + p.q)",
+                        "kernel_bytes64": kern64_bytes, "kernel_GBps64": round(kern64_bytes / (spmv_avg_ms * 1e-3) / 1e9, 1),
+                        "kernel_bytes32": kern32_bytes,
+                        "kernel_GBps32": round(kern32_bytes / (spmv32_avg_ms * 1e-3) / 1e9, 1)},
+        "roofline": {"bound": "hbm", "kernel": "cg_spmv_pq<double> (FP64 SpMV + p.q; offset-coded row groups)",
                      "achieved": round(spmv_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(spmv_gbs / HBM_PEAK_GBS, 4),
-                     "bytes_per_launch": spmv64_bytes, "avg_launch_ms": round(spmv_avg_ms, 5),
+                     "bytes_per_launch": spmv64_bytes, "bytes_basis": "12 nnz + 20 n + 4 (FP64 CSR SpMV)",
+                     "kernel_bytes_per_launch": kern64_bytes, "avg_launch_ms": round(spmv_avg_ms, 5),
                      "launches": n_spmv, "traffic": profiled_traffic(a.config),
                      "traffic_note": "HBM bytes/launch from FETCH_SIZE+WRITE_SIZE (profiles/traffic_c3.md), "
                                      "scaled by a 2 GiB copy; null if the kernel changed since"},

@@ -351,6 +351,96 @@ done:
     return status;
 }
 
+/* BiCGStab with Jacobi right preconditioning, M = diag(A): the Krylov
+ * solver the paper's benchmark uses for the non-symmetric momentum system
+ * (Sec. 4), in the stabilised form of van der Vorst (SIAM J. Sci. Stat.
+ * Comput. 13, 1992), as Saad, Iterative Methods for Sparse Linear Systems,
+ * 2nd ed., Alg. 7.7, with the preconditioner applied on the right
+ * (A M^-1 u = b, x = M^-1 u):
+ *   r = b - A x, rh = r, rho0 = alpha = omega = 1, v = p = 0
+ *   repeat:  rho = (rh, r);  beta = (rho / rho0) (alpha / omega)
+ *            p = r + beta (p - omega v);  y = M^-1 p;  v = A y
+ *            alpha = rho / (rh, v);  s = r - alpha v
+ *            if ||s|| <= tol ||b||:  x = x + alpha y, stop
+ *            z = M^-1 s;  t = A z;  omega = (t, s) / (t, t)
+ *            x = (x + alpha y) + omega z;  r = s - omega t;  rho0 = rho
+ *            if ||r|| <= tol ||b||: stop
+ * One iteration is one pass (two products with A).  A stop on the recurrence
+ * residual is confirmed on b - A x; if that fails the method restarts from
+ * the current x with rh = r (at most max_restarts times).  rho, (rh, v) or
+ * (t, t) equal to 0 or not finite, or omega = 0, is a breakdown.
+ * out[0] = iterations, out[1] = restarts; res[0] = true relative residual. */
+int or_bicgstab(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                const double* b, double* x, double tol, int64_t max_iter, int max_restarts,
+                int64_t* out, double* res)
+{
+    const size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *diag = (double*)malloc(sz), *r = (double*)malloc(sz), *rh = (double*)malloc(sz);
+    double *p = (double*)malloc(sz), *v = (double*)malloc(sz), *y = (double*)malloc(sz);
+    double *s = (double*)malloc(sz), *z = (double*)malloc(sz), *t = (double*)malloc(sz);
+    int status = OR_NOT_CONVERGED;
+    int64_t it = 0;
+    int restarts = 0;
+
+    for (int64_t i = 0; i < n; ++i) {
+        diag[i] = 0.0;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            if (col[k] == i) diag[i] = val[k];
+    }
+    const double bnorm = sqrt(dot(n, b, b));
+    if (bnorm == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        status = OR_OK;
+        goto done;
+    }
+    for (;;) {
+        or_spmv(n, row_ptr, col, val, x, t);
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i] - t[i];
+        if (sqrt(dot(n, r, r)) <= tol * bnorm) { status = OR_OK; break; }
+        for (int64_t i = 0; i < n; ++i) { rh[i] = r[i]; p[i] = 0.0; v[i] = 0.0; }
+        double rho0 = 1.0, alpha = 1.0, omega = 1.0;
+        int passed = 0;
+        while (it < max_iter) {
+            const double rho = dot(n, rh, r);
+            if (rho == 0.0 || !isfinite(rho)) { status = OR_ERR_BREAKDOWN; goto done; }
+            const double beta = (rho / rho0) * (alpha / omega);
+            for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+            for (int64_t i = 0; i < n; ++i) y[i] = p[i] / diag[i];
+            or_spmv(n, row_ptr, col, val, y, v);
+            const double rv = dot(n, rh, v);
+            if (rv == 0.0 || !isfinite(rv)) { status = OR_ERR_BREAKDOWN; goto done; }
+            alpha = rho / rv;
+            for (int64_t i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
+            ++it;
+            if (sqrt(dot(n, s, s)) <= tol * bnorm) {
+                for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * y[i];
+                passed = 1;
+                break;
+            }
+            for (int64_t i = 0; i < n; ++i) z[i] = s[i] / diag[i];
+            or_spmv(n, row_ptr, col, val, z, t);
+            const double tt = dot(n, t, t);
+            if (tt == 0.0 || !isfinite(tt)) { status = OR_ERR_BREAKDOWN; goto done; }
+            omega = dot(n, t, s) / tt;
+            for (int64_t i = 0; i < n; ++i) x[i] = (x[i] + alpha * y[i]) + omega * z[i];
+            for (int64_t i = 0; i < n; ++i) r[i] = s[i] - omega * t[i];
+            rho0 = rho;
+            if (sqrt(dot(n, r, r)) <= tol * bnorm) { passed = 1; break; }
+            if (omega == 0.0) { status = OR_ERR_BREAKDOWN; goto done; }
+        }
+        if (!passed) break;                     /* iteration budget spent */
+        if (or_true_relres(n, row_ptr, col, val, b, x) <= tol) { status = OR_OK; break; }
+        if (restarts >= max_restarts) break;
+        ++restarts;
+    }
+done:
+    out[0] = it;
+    out[1] = restarts;
+    res[0] = or_true_relres(n, row_ptr, col, val, b, x);
+    free(diag); free(r); free(rh); free(p); free(v); free(y); free(s); free(z); free(t);
+    return status;
+}
+
 /* Gradient of L with respect to every receive-buffer slot for A x = b:
  * dL/dv_k = −lambda_row(k) · x_col(k), lambda = A^-T dL/dx.  Columns are
  * global ids; only local slots (column inside [lo, lo + n_rows)) are defined,

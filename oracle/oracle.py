@@ -52,6 +52,7 @@ def loaded_library():
         lib.or_true_relres.restype = C.c_double
         lib.or_pcg.argtypes = [C.c_int64, _I32, _I32, _F64, _F64, _F64, C.c_double, C.c_int64, C.c_int,
                                _I64, _F64]
+        lib.or_bicgstab.argtypes = lib.or_pcg.argtypes
         lib.or_value_grad.argtypes = [C.c_int64, _I32, _I64, C.c_int64, C.c_int64, _F64, _F64, _F64]
         lib.or_face_grad.argtypes = [C.c_int64, _I64, _I64, _F64, _F64, _F64]
         _lib = lib
@@ -185,6 +186,29 @@ def pcg(m: Merged, val64, b, x0=None, tol=1e-8, max_iter=100000, max_restarts=5)
                     np.ascontiguousarray(b, dtype=np.float64), x, float(tol), int(max_iter), int(max_restarts),
                     out, res)
     return x, int(st), int(out[0]), int(out[1]), float(res[0])
+
+
+def bicgstab_csr(row_ptr, col, val, b, x0=None, tol=1e-8, max_iter=100000, max_restarts=5):
+    """Jacobi right-preconditioned BiCGStab on a CSR matrix (the momentum
+    solver of Sec. 4; van der Vorst 1992, Saad Alg. 7.7).  Returns (x, status,
+    iterations, restarts, true relative residual)."""
+    lib = loaded_library()
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    n = row_ptr.shape[0] - 1
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    out = np.zeros(2, np.int64)
+    res = np.zeros(1)
+    st = lib.or_bicgstab(n, row_ptr, _i32(col), np.ascontiguousarray(val, dtype=np.float64),
+                         np.ascontiguousarray(b, dtype=np.float64), x, float(tol), int(max_iter), int(max_restarts),
+                         out, res)
+    return x, int(st), int(out[0]), int(out[1]), float(res[0])
+
+
+def bicgstab(m: Merged, val64, b, x0=None, tol=1e-8, max_iter=100000, max_restarts=5):
+    """BiCGStab (as bicgstab_csr) on the fused local block."""
+    if m.nnz_nonlocal:
+        raise OracleError(-5, "bicgstab (non-local block present)")
+    return bicgstab_csr(m.row_ptr, m.col[:m.nnz_local], val64[:m.nnz_local], b, x0, tol, max_iter, max_restarts)
 
 
 def value_grad(m: Merged, lam, x) -> np.ndarray:

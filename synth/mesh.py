@@ -289,16 +289,20 @@ def cell_diagonal(mesh: Mesh, c: np.ndarray) -> np.ndarray:
 @dataclass
 class LduValues:
     """Per-rank LDU values concatenated over ranks, slices as in Partition.
-    The matrix is symmetric: lower == upper (not stored separately)."""
+    lower is None for a symmetric matrix (lower == upper, not stored)."""
     diag: np.ndarray    # float64[N]       by rank, local cell order
     upper: np.ndarray   # float64[faces]   A(owner, neighbour)
     iface: np.ndarray   # float64[ifaces]  A(cell, cell across the interface)
+    lower: np.ndarray | None = None   # float64[faces]  A(neighbour, owner)
 
     def rank(self, part: Partition, r: int) -> dict:
         c0, c1 = part.cell_ptr[r], part.cell_ptr[r + 1]
         f0, f1 = part.face_ptr[r], part.face_ptr[r + 1]
         i0, i1 = part.if_ptr[r], part.if_ptr[r + 1]
-        return dict(diag=self.diag[c0:c1], upper=self.upper[f0:f1], iface=self.iface[i0:i1])
+        out = dict(diag=self.diag[c0:c1], upper=self.upper[f0:f1], iface=self.iface[i0:i1])
+        if self.lower is not None:
+            out["lower"] = self.lower[f0:f1]
+        return out
 
 
 def ldu_values(mesh: Mesh, part: Partition, c: np.ndarray) -> LduValues:
@@ -306,3 +310,66 @@ def ldu_values(mesh: Mesh, part: Partition, c: np.ndarray) -> LduValues:
     return LduValues(diag=diag_nat[part.rank_cells],
                      upper=-c[part.face_gid],
                      iface=-c[part.if_gid])
+
+
+# ----------------------------------------------------------------------------
+# non-symmetric convection-diffusion (momentum-type) values
+# ----------------------------------------------------------------------------
+def stream_fluxes(mesh: Mesh) -> np.ndarray:
+    """Face fluxes along +axis (from face_a to face_b) of a rotating flow in
+    every x-y plane, from the stream function psi(X, Y) = sin(pi X) sin(pi Y)
+    at the cell corners X = i / nx, Y = j / ny: an x face carries
+    (psi(top corner) - psi(bottom corner)) dz_k, a y face
+    -(psi(right) - psi(left)) dz_k, z faces and walls none.  The four fluxes
+    of a cell cancel, so the flow is divergence-free cell by cell."""
+    nx, ny, nz = mesh.nx, mesh.ny, mesh.nz
+    X = np.arange(nx + 1) / nx
+    Y = np.arange(ny + 1) / ny
+    psi = np.sin(np.pi * X)[None, :] * np.sin(np.pi * Y)[:, None]      # [ny+1, nx+1]
+    dz = mesh.dz
+    # x faces between i and i+1 (i < nx-1), in (k, j, i) order
+    fx = (psi[1:, 1:nx] - psi[:-1, 1:nx])[None, :, :] * dz[:, None, None]            # [nz, ny, nx-1]
+    # y faces between j and j+1 (j < ny-1)
+    fy = -(psi[1:ny, 1:] - psi[1:ny, :-1])[None, :, :] * dz[:, None, None]           # [nz, ny-1, nx]
+    fz = np.zeros((nz - 1) * ny * nx)
+    flux = np.zeros(mesh.n_faces)
+    interior = np.concatenate([fx.ravel(), fy.ravel(), fz])
+    assert interior.shape[0] == mesh.n_interior
+    flux[:mesh.n_interior] = interior
+    return flux
+
+
+def momentum_ldu(mesh: Mesh, part: Partition, c: np.ndarray, flux: np.ndarray, sigma: np.ndarray) -> LduValues:
+    """Upwind convection-diffusion matrix with a transient term: for an
+    interior face a -> b with diffusion coefficient c_f and flux F_f,
+    A(a, b) = -(c_f + max(-F_f, 0)) and A(b, a) = -(c_f + max(F_f, 0)); the
+    diagonal of a cell sums c_f + max(F_out, 0) over its faces (walls: c_w)
+    in ascending global face order, then adds sigma of the cell.  With a
+    divergence-free flux the matrix is a diagonally dominant M-matrix,
+    non-symmetric wherever F_f != 0."""
+    ni, nf = mesh.n_interior, mesh.n_faces
+    a, b = mesh.face_a, mesh.face_b
+    F = flux[:ni]
+    a_ab = -(c[:ni] + np.maximum(-F, 0.0))      # A(a, b)
+    a_ba = -(c[:ni] + np.maximum(F, 0.0))       # A(b, a)
+    cells = np.empty(2 * ni + (nf - ni), dtype=np.int64)
+    w = np.empty(cells.shape[0], dtype=np.float64)
+    cells[0:2 * ni:2] = a[:ni]
+    cells[1:2 * ni:2] = b[:ni]
+    w[0:2 * ni:2] = c[:ni] + np.maximum(F, 0.0)
+    w[1:2 * ni:2] = c[:ni] + np.maximum(-F, 0.0)
+    cells[2 * ni:] = a[ni:]
+    w[2 * ni:] = c[ni:]
+    diag_nat = np.bincount(cells, weights=w, minlength=mesh.n_cells) + sigma
+
+    # internal faces: is the rank-local owner the mesh's minus side?
+    f_rank = np.repeat(np.arange(part.n_ranks), np.diff(part.face_ptr))
+    own_nat = part.rank_cells[part.cell_ptr[f_rank] + part.owner]
+    fwd = own_nat == a[part.face_gid]
+    upper = np.where(fwd, a_ab[part.face_gid], a_ba[part.face_gid])
+    lower = np.where(fwd, a_ba[part.face_gid], a_ab[part.face_gid])
+    # interfaces: the entry of the passing rank's own row
+    i_rank = np.repeat(np.arange(part.n_ranks), np.diff(part.if_ptr))
+    cell_nat = part.rank_cells[part.cell_ptr[i_rank] + part.if_cell]
+    iface = np.where(cell_nat == a[part.if_gid], a_ab[part.if_gid], a_ba[part.if_gid])
+    return LduValues(diag=diag_nat[part.rank_cells], upper=upper, iface=iface, lower=lower)

@@ -19,7 +19,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .mesh import (Mesh, Partition, LduValues, structured_mesh, stretched_dz,
-                   decompose_blocks, decompose_rcb, partition, ldu_values)
+                   decompose_blocks, decompose_rcb, partition, ldu_values, stream_fluxes, momentum_ldu)
 
 
 @dataclass
@@ -87,6 +87,19 @@ class Workload:
 
     def values(self, t: int | None = None) -> LduValues:
         return ldu_values(self.mesh, self.part, self.coefficients(t))
+
+    def momentum_values(self, t: int | None = None, pe: float = 4.0, sigma: float = 1.0) -> LduValues:
+        """Non-symmetric momentum-type matrix on the same mesh and ranks:
+        diffusion c_f = coefficients(t), the rotating flux of stream_fluxes
+        scaled so its largest face flux is pe * median(c), and a transient
+        term sigma * median(c) on every diagonal."""
+        c = self.coefficients(t)
+        cm = float(np.median(c))
+        flux = stream_fluxes(self.mesh)
+        fmax = float(np.abs(flux).max())
+        if fmax > 0.0:
+            flux = flux * (pe * cm / fmax)
+        return momentum_ldu(self.mesh, self.part, c, flux, np.full(self.mesh.n_cells, sigma * cm))
 
     def merged(self, v_nat: np.ndarray, first: int = 0, alpha: int | None = None) -> np.ndarray:
         """A natural-order cell field in merged order: the share's ranks in

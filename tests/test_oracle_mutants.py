@@ -34,6 +34,16 @@ MUTANTS = {
                                  "z[i] = r[i];\n            const double rz_new"),
     # CG: preconditioner left out everywhere
     "cg_no_precond": ("z[i] = r[i] / diag[i];", "z[i] = r[i];"),
+    # BiCGStab: the omega v correction left out of the direction update
+    "bicg_p_no_omega_v": ("p[i] = r[i] + beta * (p[i] - omega * v[i]);", "p[i] = r[i] + beta * p[i];"),
+    # BiCGStab: intermediate residual with the wrong sign
+    "bicg_s_sign": ("s[i] = r[i] - alpha * v[i];", "s[i] = r[i] + alpha * v[i];"),
+    # BiCGStab: preconditioner left out of the stabilising half step
+    "bicg_z_no_precond": ("z[i] = s[i] / diag[i];", "z[i] = s[i];"),
+    # BiCGStab: shadow residual replaced by the current residual
+    "bicg_rho_uses_r": ("const double rho = dot(n, rh, r);", "const double rho = dot(n, r, r);"),
+    # BiCGStab: omega step missing from the solution update
+    "bicg_x_no_omega": ("x[i] = (x[i] + alpha * y[i]) + omega * z[i];", "x[i] = x[i] + alpha * y[i];"),
     # adjoint: row and column exchanged
     "grad_transposed": ("-lambda[slot_row[k]] * x[c]", "-lambda[c] * x[slot_row[k]]"),
     # adjoint: interface face gradient sign of the partner term
@@ -50,6 +60,9 @@ PIN_CALLS = [
     pins.test_p5_two_eigenvalues_two_iterations,
     lambda: [pins.test_p6_tridiagonal_inverse(n) for n in (1, 3)],
     lambda: [pins.test_p7_dense_lu(c) for c in range(1, len(pins.SMALL_CASES))],
+    pins.test_p9_bicgstab_diagonal_one_iteration,
+    pins.test_p9_bicgstab_two_eigenvalues_two_iterations,
+    lambda: [pins.test_p9_bicgstab_dense_lu(c) for c in range(1, len(pins.SMALL_CASES))],
     pins.test_p8_slot_gradient_dense,
     pins.test_p8_adjoint_face_gradient_finite_difference,
 ]

@@ -2,7 +2,8 @@
 
 Each test names what fixes the result: the undecomposed global assembly, a
 brute-force dense build, a hand-derived example, closed-form solutions of the
-1D and 3D Poisson problems, dense LU, and finite differences for the adjoint.
+1D and 3D Poisson problems, dense LU, finite differences for the adjoint, and
+(P9) the termination properties of BiCGStab on non-symmetric systems.
 """
 import json
 import os
@@ -359,6 +360,95 @@ def test_p7_stopping_rule_and_zero_rhs():
         assert st1 == 1 and it1 == it - 1
     x, st, it, rs, rr = oracle.pcg(m, val64, np.zeros(m.n_rows), x0=np.ones(m.n_rows))
     assert st == 0 and it == 0 and (x == 0).all()
+
+
+# --------------------------------------------------------------------------
+# P9: BiCGStab on non-symmetric (momentum-type) systems
+# --------------------------------------------------------------------------
+def _momentum_system(case, seed, **kw):
+    w = _small(case, seed=seed)
+    v = w.momentum_values(**kw)
+    m = oracle.merge(w.part.n_cells, 0, w.n_ranks, share_ranks(w))
+    val64, *_ = oracle.update(m, oracle.receive_buffer(share_values(w, values=v)))
+    A = sp.csr_matrix((val64, m.col, m.row_ptr), shape=(m.n_rows, m.n_rows)).toarray()
+    return w, m, val64, A
+
+
+@pytest.mark.parametrize("case", range(1, len(SMALL_CASES)))
+def test_p9_bicgstab_dense_lu(case):
+    """Non-symmetric convection-diffusion systems, blocked and scrambled RCB
+    numberings: BiCGStab against a dense LU solve."""
+    w, m, val64, A = _momentum_system(case, 900, pe=6.0)
+    assert np.abs(A - A.T).max() > 1e-3          # genuinely non-symmetric
+    b = w.rhs()
+    xl = np.linalg.solve(A, b)
+    x, st, it, rs, rr = oracle.bicgstab(m, val64, b, tol=1e-12)
+    assert st == 0 and rr <= 1e-12
+    assert np.linalg.norm(b - A @ x) <= 1e-12 * np.linalg.norm(b) * (1 + 1e-9)
+    assert np.linalg.norm(x - xl) <= 1e-8 * np.linalg.norm(xl)
+
+
+def test_p9_bicgstab_diagonal_one_iteration():
+    """M = diag(A) makes A M^-1 = I for a diagonal A: one iteration, x = b / d."""
+    n = 37
+    rng = np.random.default_rng(91)
+    d = rng.uniform(0.5, 50.0, n)
+    ranks = [dict(owner=np.zeros(0, np.int32), neighbour=np.zeros(0, np.int32), iface_cell=np.zeros(0, np.int32),
+                  iface_nbr_rank=np.zeros(0, np.int32), iface_nbr_cell=np.zeros(0, np.int32))]
+    m = oracle.merge([n], 0, 1, ranks)
+    val64, *_ = oracle.update(m, oracle.receive_buffer([dict(diag=d, upper=np.zeros(0), iface=np.zeros(0))]))
+    b = rng.uniform(-1, 1, n)
+    x, st, it, rs, rr = oracle.bicgstab(m, val64, b, tol=1e-8)
+    assert st == 0 and it == 1 and rs == 0
+    assert np.max(np.abs(x - b / d) / np.abs(b / d)) < 1e-14
+
+
+def test_p9_bicgstab_two_eigenvalues_two_iterations():
+    """Non-symmetric 2x2 blocks [[a, u], [w, e]] with u w = rho^2 a e give
+    A M^-1 the eigenvalues 1 +- rho only: the BiCG polynomial of degree two
+    annihilates the residual, so BiCGStab ends within two iterations."""
+    m_pairs, rho = 40, 0.5
+    rng = np.random.default_rng(92)
+    a, e = rng.uniform(1, 100, m_pairs), rng.uniform(1, 100, m_pairs)
+    s = rng.uniform(0.2, 5.0, m_pairs)                 # u / w: the blocks are not symmetric
+    u = -rho * np.sqrt(a * e * s)
+    wv = -rho * np.sqrt(a * e / s)
+    n = 2 * m_pairs
+    ranks = [dict(owner=np.arange(0, n, 2, dtype=np.int32), neighbour=np.arange(1, n, 2, dtype=np.int32),
+                  iface_cell=np.zeros(0, np.int32), iface_nbr_rank=np.zeros(0, np.int32),
+                  iface_nbr_cell=np.zeros(0, np.int32))]
+    diag = np.empty(n)
+    diag[0::2], diag[1::2] = a, e
+    m = oracle.merge([n], 0, 1, ranks)
+    val64, *_ = oracle.update(m, oracle.receive_buffer([dict(diag=diag, upper=u, lower=wv, iface=np.zeros(0))]))
+    rhs = rng.uniform(-1, 1, n)
+    x, st, it, rs, rr = oracle.bicgstab(m, val64, rhs, tol=1e-10)
+    assert st == 0 and it <= 2 and rs == 0
+    A = sp.csr_matrix((val64, m.col, m.row_ptr), shape=(n, n)).toarray()
+    assert np.abs(A - A.T).max() > 1.0
+    assert np.linalg.norm(A @ x - rhs) <= 1e-10 * np.linalg.norm(rhs)
+
+
+def test_p9_bicgstab_stopping_rule_and_zero_rhs():
+    w, m, val64, A = _momentum_system(3, 901)
+    b = w.rhs()
+    for tol in (1e-4, 1e-8):
+        x, st, it, rs, rr = oracle.bicgstab(m, val64, b, tol=tol)
+        assert st == 0 and rr <= tol and it >= 2
+        x1, st1, it1, _, rr1 = oracle.bicgstab(m, val64, b, tol=tol, max_iter=it - 1)
+        assert st1 == 1 and it1 == it - 1 and rr1 > tol
+    x, st, it, rs, rr = oracle.bicgstab(m, val64, np.zeros(m.n_rows), x0=np.ones(m.n_rows))
+    assert st == 0 and it == 0 and (x == 0).all()
+
+
+def test_p9_bicgstab_symmetric_agrees_with_cg():
+    """On the symmetric pressure matrix both Krylov methods reach the same x."""
+    w = _small(4, seed=902)
+    m, buf, val64, *_ = oracle_system(w)
+    b = w.rhs()
+    xc, *_ = oracle.pcg(m, val64, b, tol=1e-12)
+    xb, st, it, rs, rr = oracle.bicgstab(m, val64, b, tol=1e-12)
+    assert st == 0 and np.linalg.norm(xb - xc) <= 1e-9 * np.linalg.norm(xc)
 
 
 # --------------------------------------------------------------------------

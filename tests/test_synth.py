@@ -87,3 +87,89 @@ def test_stretched_spacing():
     dz = synth.stretched_dz(160, 100.0)
     assert dz[0] == 1.0 and abs(dz[-1] - 0.01) < 1e-15
     assert (np.diff(dz) < 0).all()
+
+
+# --------------------------------------------------------------------------
+# non-symmetric momentum-type values
+# --------------------------------------------------------------------------
+MOMENTUM_CASES = [((7, 6, 5), ("blocks", 2, 3, 1), dict(kappa=(1e-2, 1.0))),
+                  ((6, 5, 7), ("rcb", 5), dict(kappa=(1e-3, 1.0), scramble=True, stretch=100.0))]
+
+
+def _global_momentum(w, pe, sigma):
+    """The operator assembled straight from the undecomposed face arrays:
+    A(a,b) = -(c + max(-F,0)), A(b,a) = -(c + max(F,0)); diag as the sum of
+    c + max(F_out, 0) over faces (walls c) plus sigma (natural numbering)."""
+    mesh = w.mesh
+    c = w.coefficients()
+    cm = float(np.median(c))
+    F = synth.stream_fluxes(mesh)
+    F = F * (pe * cm / np.abs(F).max())
+    n, ni = mesh.n_cells, mesh.n_interior
+    A = np.zeros((n, n))
+    d = np.zeros(n)
+    for f in range(mesh.n_faces):
+        a, b = mesh.face_a[f], mesh.face_b[f]
+        if f < ni:
+            A[a, b] = -(c[f] + max(-F[f], 0.0))
+            A[b, a] = -(c[f] + max(F[f], 0.0))
+            d[a] += c[f] + max(F[f], 0.0)
+            d[b] += c[f] + max(-F[f], 0.0)
+        else:
+            d[a] += c[f]
+    A[np.arange(n), np.arange(n)] = d + sigma * cm
+    return A, F
+
+
+@pytest.mark.parametrize("case", range(len(MOMENTUM_CASES)))
+def test_momentum_values_match_global_assembly(case):
+    """Per-rank upper / lower / interface values place every entry of the
+    global operator at its (row, column), bit for bit: checks the orientation
+    of each rank's faces and interfaces against the mesh."""
+    shape, decomp, kw = MOMENTUM_CASES[case]
+    w = synth.small(shape, decomp, seed=40 + case, **kw)
+    pe, sigma = 5.0, 0.5
+    A, F = _global_momentum(w, pe, sigma)
+    v = w.momentum_values(pe=pe, sigma=sigma)
+    p = w.part
+    nat = p.rank_cells
+    got = np.zeros_like(A)
+    for r in range(w.n_ranks):
+        d = p.rank(r)
+        vr = v.rank(p, r)
+        base = p.cell_ptr[r]
+        cells = nat[base:base + d["n_cells"]]
+        got[cells, cells] = vr["diag"]
+        got[cells[d["owner"]], cells[d["neighbour"]]] = vr["upper"]
+        got[cells[d["neighbour"]], cells[d["owner"]]] = vr["lower"]
+        nb = nat[p.cell_ptr[d["iface_nbr_rank"]] + d["iface_nbr_cell"]]
+        got[cells[d["iface_cell"]], nb] = vr["iface"]
+    assert np.array_equal(got.view(np.uint64), A.view(np.uint64))
+    assert np.abs(A - A.T).max() > 0.1 * np.abs(F).max()
+
+
+@pytest.mark.parametrize("case", range(len(MOMENTUM_CASES)))
+def test_momentum_m_matrix_and_divergence_free(case):
+    shape, decomp, kw = MOMENTUM_CASES[case]
+    w = synth.small(shape, decomp, seed=50 + case, **kw)
+    mesh = w.mesh
+    F = synth.stream_fluxes(mesh)
+    ni = mesh.n_interior
+    div = np.zeros(mesh.n_cells)
+    np.add.at(div, mesh.face_a[:ni], F[:ni])
+    np.add.at(div, mesh.face_b[:ni], -F[:ni])
+    assert np.abs(div).max() <= 1e-14 * np.abs(F).max() and np.abs(F).max() > 0
+    assert (F[ni:] == 0).all()
+    v = w.momentum_values(pe=8.0, sigma=1.0)
+    assert (v.upper < 0).all() and (v.lower < 0).all() and (v.iface < 0).all() and (v.diag > 0).all()
+    A, _ = _global_momentum(w, 8.0, 1.0)
+    sigma = np.median(w.coefficients())
+    # row sums: sigma + wall coefficients + net outflow (0): every row dominant
+    assert (A.sum(axis=1) >= sigma * (1 - 1e-9)).all()
+
+
+def test_momentum_without_flux_is_pressure_plus_sigma():
+    w = synth.small((6, 5, 4), ("blocks", 2, 1, 2), seed=60, kappa=(1e-2, 1.0))
+    v0, vp = w.momentum_values(pe=0.0, sigma=0.0), w.values()
+    assert np.array_equal(v0.upper, vp.upper) and np.array_equal(v0.lower, vp.upper)
+    assert np.array_equal(v0.iface, vp.iface) and np.array_equal(v0.diag, vp.diag)
