@@ -56,9 +56,10 @@ extern "C" {
                                      duplicate matrix entry, unpaired interface */
 #define RP_ERR_OVERFLOW (-3)      /* rows or slots of the share reach 2^31 */
 #define RP_ERR_HIP (-4)           /* a HIP runtime call failed */
-#define RP_ERR_UNSUPPORTED (-5)   /* solve with a non-empty non-local block or a
-                                     non-symmetric matrix */
-#define RP_ERR_BREAKDOWN (-6)     /* CG breakdown: p.Ap <= 0 or not finite */
+#define RP_ERR_UNSUPPORTED (-5)   /* solve with a non-empty non-local block, CG on a
+                                     non-symmetric matrix, BiCGStab not in FP64 */
+#define RP_ERR_BREAKDOWN (-6)     /* CG: p.Ap <= 0 or not finite; BiCGStab: (rh, r),
+                                     (rh, v) or (t, t) zero or not finite, or omega = 0 */
 #define RP_ERR_VALUE (-7)         /* an updated value is not finite, or diag <= 0 */
 
 /* ---- precisions -------------------------------------------------------- */
@@ -66,6 +67,12 @@ extern "C" {
 #define RP_MIXED 1                /* FP32 PCG with FP64 residual-replacement updates (solve only) */
 #define RP_FP32 2                 /* FP32 matrix and vectors (rp_spmv only) */
 #define RP_MIXED_IR 3             /* FP32 inner PCG restarted under FP64 refinement (solve only) */
+
+/* ---- Krylov methods ------------------------------------------------------ */
+#define RP_CG 0                   /* Jacobi-PCG, symmetric positive definite A (the pressure
+                                     system, Sec. 4) */
+#define RP_BICGSTAB 1             /* Jacobi right-preconditioned BiCGStab, any non-singular A
+                                     (the non-symmetric momentum system, Sec. 4); FP64 only */
 
 typedef struct rp_plan rp_plan;
 
@@ -97,6 +104,7 @@ typedef struct rp_solve_opts {
     int32_t x0_zero;         /* 1: start from x = 0 and ignore x on entry */
     int32_t max_restarts;    /* FP64: restarts when the recurrence residual passes
                                 but the true residual does not (default 5) */
+    int32_t method;          /* RP_CG (default) or RP_BICGSTAB */
 } rp_solve_opts;
 
 typedef struct rp_solve_info {
@@ -199,19 +207,24 @@ int rp_update_values_slots(rp_plan* plan, const double* slots, void* stream);
  * column order with one rounding per product and per sum. */
 int rp_spmv(rp_plan* plan, int32_t precision, const void* x, void* y, void* stream);
 
-/* ---- solve (Sec. 4: CG for the pressure system) ------------------------ *
- * RP_FP64 is Jacobi-PCG in FP64.  RP_MIXED runs the same PCG in FP32 (FP32
- * matrix, preconditioner, vectors and dot products) and, whenever its
+/* ---- solve (Sec. 4: CG for the pressure system, BiCGStab for momentum) -- *
+ * opts->method = RP_CG (default): RP_FP64 is Jacobi-PCG in FP64.  RP_MIXED
+ * runs the same PCG in FP32 (FP32 matrix, preconditioner, vectors and dot
+ * products) and, whenever its
  * residual has fallen by update_delta, folds its correction into the FP64
  * solution and replaces its residual by the FP64 residual b - A x, keeping
  * the search direction; the stop test is on that FP64 residual.  RP_MIXED_IR
  * restarts an FP32 PCG (to inner_tol) on every FP64 refinement residual.
- * b, x: device arrays of n_rows doubles in fused row order (the share's
+ * opts->method = RP_BICGSTAB: BiCGStab with M = diag(A) applied on the
+ * right, in FP64, for non-symmetric matrices (van der Vorst 1992; one
+ * iteration = two products with A); its stop test and restart follow the
+ * CG's.  b, x: device arrays of n_rows doubles in fused row order (the share's
  * ranks in order, each in local cell order).  x holds x0 on entry (unless
  * opts->x0_zero) and the solution on return.  opts NULL = defaults.  Blocks
  * until the solve is finished.  Returns RP_OK, RP_NOT_CONVERGED,
- * RP_ERR_BREAKDOWN, RP_ERR_UNSUPPORTED (non-local block or non-symmetric
- * matrix), RP_ERR_VALUE (a pending update error).  b = 0 gives x = 0. */
+ * RP_ERR_BREAKDOWN, RP_ERR_UNSUPPORTED (non-local block, CG on a
+ * non-symmetric matrix, BiCGStab not in FP64), RP_ERR_VALUE (a pending update
+ * error).  b = 0 gives x = 0. */
 int rp_solve(rp_plan* plan, const double* b, double* x, const rp_solve_opts* opts,
              rp_solve_info* info, void* stream);
 

@@ -75,12 +75,13 @@ void free_plan(rp_plan* p) {
                    p->d_perm, p->d_perm_inv, p->d_nl_row_ptr, p->d_nl_col, p->d_iface_partner, p->d_recv,
                    p->d_val64, p->d_val32, p->d_dinv64, p->d_dinv32, p->d_r, p->d_p, p->d_q, p->d_r32,
                    p->d_p32, p->d_q32, p->d_x32, p->d_partials, p->d_st64, p->d_st32, p->d_st_outer,
-                   p->d_flags, p->d_goi_k, p->d_goi_off, p->d_goi_mask};
+                   p->d_flags, p->d_goi_k, p->d_goi_off, p->d_goi_mask, p->d_bi_st, p->d_bi_work};
     for (void* q : dev)
         if (q) (void)hipFree(q);
     if (p->h_st64) (void)hipHostFree(p->h_st64);
     if (p->h_st32) (void)hipHostFree(p->h_st32);
     if (p->h_st_outer) (void)hipHostFree(p->h_st_outer);
+    if (p->h_bi_st) (void)hipHostFree(p->h_bi_st);
     if (p->h_flags) (void)hipHostFree(p->h_flags);
     for (auto& e : p->timing.pool) {
         for (hipEvent_t ev : e.start) (void)hipEventDestroy(ev);
@@ -122,6 +123,9 @@ int alloc_values(rp_plan* p) {
     RP_HIP_TRY(hipHostMalloc((void**)&p->h_st64, sizeof(CgState<double>), hipHostMallocDefault));
     RP_HIP_TRY(hipHostMalloc((void**)&p->h_st32, sizeof(CgState<float>), hipHostMallocDefault));
     RP_HIP_TRY(hipHostMalloc((void**)&p->h_st_outer, sizeof(CgState<double>), hipHostMallocDefault));
+    RP_TRY(dalloc(&p->d_bi_st, 1));
+    RP_HIP_TRY(hipMemset(p->d_bi_st, 0, sizeof(BiState)));
+    RP_HIP_TRY(hipHostMalloc((void**)&p->h_bi_st, sizeof(BiState), hipHostMallocDefault));
     RP_HIP_TRY(hipHostMalloc((void**)&p->h_flags, 2 * sizeof(uint32_t), hipHostMallocDefault));
     return RP_OK;
 }
@@ -409,6 +413,7 @@ void rp_solve_opts_default(rp_solve_opts* o) {
     o->check_every = 32;
     o->x0_zero = 0;
     o->max_restarts = 5;
+    o->method = RP_CG;
 }
 
 int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, rp_solve_info* info,
@@ -428,12 +433,16 @@ int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, 
              RP_ERR_ARG, "bad solve options");
     RP_CHECK(o.precision == RP_FP64 || o.precision == RP_MIXED || o.precision == RP_MIXED_IR, RP_ERR_ARG,
              "precision must be RP_FP64, RP_MIXED or RP_MIXED_IR");
+    RP_CHECK(o.method == RP_CG || o.method == RP_BICGSTAB, RP_ERR_ARG, "method must be RP_CG or RP_BICGSTAB");
+    RP_CHECK(o.method == RP_CG || o.precision == RP_FP64, RP_ERR_UNSUPPORTED, "BiCGStab runs in FP64 only");
     RP_TRY(activate(p));
     hipStream_t s = as_stream(stream);
     p->last_stream = s;
     int rc;
     if (p->n_rows == 0) {
         rc = RP_OK;
+    } else if (o.method == RP_BICGSTAB) {
+        rc = solve_bicgstab(p, b, x, o, inf, s);
     } else if (o.precision == RP_FP64) {
         rc = solve_fp64(p, b, x, o, inf, s);
     } else {

@@ -388,14 +388,14 @@ int iterate(Cg<T>& c, int chunk, int32_t max_iter) {
     return RP_OK;
 }
 
-int pending_value_error(rp_plan* p, hipStream_t s) {
+int pending_value_error(rp_plan* p, hipStream_t s, bool need_symmetric) {
     RP_HIP_TRY(hipMemcpyAsync(p->h_flags, p->d_flags, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     RP_HIP_TRY(hipStreamSynchronize(s));
     if (p->h_flags[0] & FLAG_VALUE) {
         set_error("the last update produced a value that is not finite or a diagonal <= 0");
         return RP_ERR_VALUE;
     }
-    if (p->h_flags[1]) {
+    if (need_symmetric && p->h_flags[1]) {
         set_error("CG needs a symmetric matrix: the last update has upper != lower or unequal "
                   "interface partners");
         return RP_ERR_UNSUPPORTED;
@@ -403,7 +403,7 @@ int pending_value_error(rp_plan* p, hipStream_t s) {
     return RP_OK;
 }
 
-int check_solvable(rp_plan* p, hipStream_t s) {
+int check_solvable(rp_plan* p, hipStream_t s, bool need_symmetric = true) {
     if (!p->has_values) {
         set_error("rp_solve before any rp_update_values");
         return RP_ERR_ARG;
@@ -413,7 +413,7 @@ int check_solvable(rp_plan* p, hipStream_t s) {
                   (long long)p->nnz_nl);
         return RP_ERR_UNSUPPORTED;
     }
-    return pending_value_error(p, s);
+    return pending_value_error(p, s, need_symmetric);
 }
 
 }  // namespace
@@ -560,6 +560,375 @@ int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, 
     if (status == RP_NOT_CONVERGED)
         set_error("mixed solve not converged: %d FP64 updates, %d FP32 iterations, relative residual %g",
                   outer, total_inner, info.rel_res);
+    return status;
+}
+
+
+// ---------------------------------------------------------------------------
+// BiCGStab (non-symmetric systems; the momentum solver of Sec. 4)
+// ---------------------------------------------------------------------------
+// Jacobi right-preconditioned BiCGStab (van der Vorst 1992), iteration k as
+// five kernels; every kernel re-sums the previous kernel's partials, as in CG:
+//   A  stop test on (r, r); rho = (rh, r); beta = (rho / rho_{k-1})(alpha / omega);
+//      p = r + beta (p - omega v); y = M^-1 p
+//   B  v = A y                        partials of (rh, v)
+//   C  alpha = rho / (rh, v); s = r - alpha v; z = M^-1 s;   partials of (s, s)
+//   D  stop at the half step if (s, s) is small; t = A z;    partials of (t, s), (t, t)
+//   E  omega = (t, s) / (t, t); x = (x + alpha y) + omega z; r = s - omega t;
+//      partials of (rh, r) and (r, r)
+// A half-step stop leaves BI_HALF; E then moves x by alpha y and ends.
+namespace {
+
+// rh = r, p = v = 0; partials of (rh, r) -> PART_RZ and (r, r) -> PART_RR;
+// rho_{k-1} = alpha = omega = 1 for the first iteration k
+__global__ void __launch_bounds__(VEC_BLOCK)
+bi_start(int32_t n, int32_t k, const double* __restrict__ r, double* __restrict__ rh, double* __restrict__ p,
+         double* __restrict__ v, double* __restrict__ part, BiState* st) {
+#pragma clang fp contract(off)
+    __shared__ double red[VEC_BLOCK / 64];
+    double prr = 0.0;
+    for (int32_t i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK) {
+        const double ri = r[i];
+        rh[i] = ri;
+        p[i] = 0.0;
+        v[i] = 0.0;
+        prr += ri * ri;
+    }
+    const double b = block_sum<double, VEC_BLOCK>(prr, red);
+    if (threadIdx.x == 0) {
+        part[PART_RZ + blockIdx.x] = b;
+        part[PART_RR + blockIdx.x] = b;
+        if (blockIdx.x == 0) {
+            st->rho[(k + 3) & 3] = 1.0;
+            st->alpha = 1.0;
+            st->omega = 1.0;
+        }
+    }
+}
+
+// one block: rr_true and bb from residual_kernel's partials; with `start`
+// also the convergence threshold and the state of a (re)started iteration k
+__global__ void __launch_bounds__(VEC_BLOCK)
+bi_finalize(int32_t start, int32_t k, double tol2, int32_t g_spmv, const double* __restrict__ part, BiState* st) {
+#pragma clang fp contract(off)
+    __shared__ double red[VEC_BLOCK / 64];
+    const double rr = sum_partials_all<double, VEC_BLOCK>(part + PART_A, g_spmv, red);
+    const double bb = sum_partials_all<double, VEC_BLOCK>(part + PART_B, g_spmv, red);
+    if (threadIdx.x != 0) return;
+    st->rr_true = rr;
+    st->bb = bb;
+    if (!start) return;
+    const double thresh = tol2 * bb;
+    st->thresh = thresh;
+    st->rr = rr;
+    st->iter = k;
+    int32_t d = CG_RUNNING;
+    if (bb == 0.0) d = CG_ZERO_RHS;
+    else if (rr <= thresh) d = CG_CONVERGED;
+    st->done = d;
+}
+
+// A
+__global__ void __launch_bounds__(VEC_BLOCK)
+bi_direction(int32_t n, int32_t k, int32_t g_vec, const double* __restrict__ r, const double* __restrict__ dinv,
+             double* __restrict__ p, const double* __restrict__ v, double* __restrict__ y,
+             const double* __restrict__ part, BiState* st) {
+#pragma clang fp contract(off)
+    if (st->done != CG_RUNNING) return;
+    __shared__ double red[VEC_BLOCK / 64];
+    const double rho = sum_partials_all<double, VEC_BLOCK>(part + PART_RZ, g_vec, red);
+    const double rr = sum_partials_all<double, VEC_BLOCK>(part + PART_RR, g_vec, red);
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const double omega = st->omega;
+    int32_t stop = CG_RUNNING;
+    if (rr <= st->thresh) stop = CG_CONVERGED;
+    else if (rho == 0.0 || !isfinite(rho) || omega == 0.0) stop = CG_BREAKDOWN;
+    if (stop != CG_RUNNING) {
+        if (lead) {
+            st->rr = rr;
+            st->iter = k;
+            st->done = stop;
+        }
+        return;
+    }
+    const double beta = (rho / st->rho[(k + 3) & 3]) * (st->alpha / omega);
+    for (int32_t i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK) {
+        const double pi = r[i] + beta * (p[i] - omega * v[i]);
+        p[i] = pi;
+        y[i] = dinv[i] * pi;
+    }
+    if (lead) {
+        st->rho[k & 3] = rho;
+        st->rr = rr;
+    }
+}
+
+// B: v = A y; partials of (rh, v) -> PART_A
+template <int NW>
+__global__ void __launch_bounds__(SPMV_BLOCK)
+bi_spmv_rv(int32_t n, SpmvIdx ix, const double* __restrict__ val, const double* __restrict__ y,
+           double* __restrict__ v, const double* __restrict__ rh, double* __restrict__ part, const BiState* st,
+           XWin w) {
+#pragma clang fp contract(off)
+    if (st->done != CG_RUNNING) return;
+    __shared__ __align__(16) double lds[SPMV_CAP];
+    __shared__ double xs[XWinSize<NW>::value];
+    __shared__ double red[SPMV_BLOCK / 64];
+    double prv = 0.0;
+    const GroupRange gr = block_groups(n);
+    for (int32_t g = gr.g0; g < gr.n_groups; g += gr.step) {
+        const int32_t r0 = g * SPMV_BLOCK;
+        const int32_t nr = min(SPMV_BLOCK, n - r0);
+        const GroupRow<double> gr_ = spmv_group_row<double, NW>(ix, val, y, n, g, nr, w, xs, lds);
+        if ((int32_t)threadIdx.x < nr) {
+            const int32_t i = r0 + threadIdx.x;
+            v[i] = gr_.s;
+            prv += rh[i] * gr_.s;
+        }
+    }
+    const double b = block_sum<double, SPMV_BLOCK>(prv, red);
+    if (threadIdx.x == 0) part[PART_A + xcd_block()] = b;
+}
+
+// C: alpha = rho / (rh, v); s = r - alpha v; z = M^-1 s; partials of (s, s) -> PART_RR
+__global__ void __launch_bounds__(VEC_BLOCK)
+bi_half(int32_t n, int32_t k, int32_t g_spmv, const double* __restrict__ r, const double* __restrict__ v,
+        const double* __restrict__ dinv, double* __restrict__ s, double* __restrict__ z, double* __restrict__ part,
+        BiState* st) {
+#pragma clang fp contract(off)
+    if (st->done != CG_RUNNING) return;
+    __shared__ double red[VEC_BLOCK / 64];
+    const double rv = sum_partials_all<double, VEC_BLOCK>(part + PART_A, g_spmv, red);
+    if (rv == 0.0 || !isfinite(rv)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->iter = k;
+            st->done = CG_BREAKDOWN;
+        }
+        return;
+    }
+    const double a = st->rho[k & 3] / rv;
+    double pss = 0.0;
+    for (int32_t i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK) {
+        const double si = r[i] - a * v[i];
+        s[i] = si;
+        z[i] = dinv[i] * si;
+        pss += si * si;
+    }
+    const double b = block_sum<double, VEC_BLOCK>(pss, red);
+    if (threadIdx.x == 0) {
+        part[PART_RR + blockIdx.x] = b;
+        if (blockIdx.x == 0) st->alpha = a;
+    }
+}
+
+// D: half-step stop test on (s, s); t = A z; partials of (t, s) -> PART_A, (t, t) -> PART_B
+template <int NW>
+__global__ void __launch_bounds__(SPMV_BLOCK)
+bi_spmv_ts(int32_t n, int32_t g_vec, SpmvIdx ix, const double* __restrict__ val, const double* __restrict__ z,
+           double* __restrict__ t, const double* __restrict__ s, double* __restrict__ part, BiState* st, XWin w) {
+#pragma clang fp contract(off)
+    if (st->done != CG_RUNNING) return;
+    __shared__ __align__(16) double lds[SPMV_CAP];
+    __shared__ double xs[XWinSize<NW>::value];
+    __shared__ double red[SPMV_BLOCK / 64];
+    const double ss = sum_partials_all<double, VEC_BLOCK>(part + PART_RR, g_vec, red);
+    if (ss <= st->thresh) {
+        if (xcd_block() == 0 && threadIdx.x == 0) {
+            st->rr = ss;
+            st->done = BI_HALF;
+        }
+        return;
+    }
+    double pts = 0.0, ptt = 0.0;
+    const GroupRange gr = block_groups(n);
+    for (int32_t g = gr.g0; g < gr.n_groups; g += gr.step) {
+        const int32_t r0 = g * SPMV_BLOCK;
+        const int32_t nr = min(SPMV_BLOCK, n - r0);
+        const GroupRow<double> gr_ = spmv_group_row<double, NW>(ix, val, z, n, g, nr, w, xs, lds);
+        if ((int32_t)threadIdx.x < nr) {
+            const int32_t i = r0 + threadIdx.x;
+            t[i] = gr_.s;
+            pts += gr_.s * s[i];
+            ptt += gr_.s * gr_.s;
+        }
+    }
+    const double b1 = block_sum<double, SPMV_BLOCK>(pts, red);
+    const double b2 = block_sum<double, SPMV_BLOCK>(ptt, red);
+    if (threadIdx.x == 0) {
+        part[PART_A + xcd_block()] = b1;
+        part[PART_B + xcd_block()] = b2;
+    }
+}
+
+// E: omega = (t, s) / (t, t); x = (x + alpha y) + omega z; r = s - omega t;
+// partials of (rh, r) -> PART_RZ and (r, r) -> PART_RR.  After a half-step
+// stop: x += alpha y only.
+__global__ void __launch_bounds__(VEC_BLOCK)
+bi_update(int32_t n, int32_t k, int32_t g_spmv, double* __restrict__ x, const double* __restrict__ y,
+          const double* __restrict__ z, const double* __restrict__ s, const double* __restrict__ t,
+          const double* __restrict__ rh, double* __restrict__ r, double* __restrict__ part, BiState* st) {
+#pragma clang fp contract(off)
+    const int32_t d = st->done;
+    if (d != CG_RUNNING && d != BI_HALF) return;
+    __shared__ double red[VEC_BLOCK / 64];
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const double a = st->alpha;
+    const int32_t i0 = blockIdx.x * VEC_BLOCK + threadIdx.x, di = gridDim.x * VEC_BLOCK;
+    if (d == BI_HALF) {
+        for (int32_t i = i0; i < n; i += di) x[i] = x[i] + a * y[i];
+        if (lead) {
+            st->iter = k + 1;
+            st->done = CG_CONVERGED;
+        }
+        return;
+    }
+    const double ts = sum_partials_all<double, VEC_BLOCK>(part + PART_A, g_spmv, red);
+    const double tt = sum_partials_all<double, VEC_BLOCK>(part + PART_B, g_spmv, red);
+    if (tt == 0.0 || !isfinite(tt)) {
+        if (lead) {
+            st->iter = k + 1;
+            st->done = CG_BREAKDOWN;
+        }
+        return;
+    }
+    const double omega = ts / tt;
+    double prho = 0.0, prr = 0.0;
+    for (int32_t i = i0; i < n; i += di) {
+        const double xi = (x[i] + a * y[i]) + omega * z[i];
+        const double ri = s[i] - omega * t[i];
+        x[i] = xi;
+        r[i] = ri;
+        prho += rh[i] * ri;
+        prr += ri * ri;
+    }
+    const double b1 = block_sum<double, VEC_BLOCK>(prho, red);
+    const double b2 = block_sum<double, VEC_BLOCK>(prr, red);
+    if (threadIdx.x == 0) {
+        part[PART_RZ + blockIdx.x] = b1;
+        part[PART_RR + blockIdx.x] = b2;
+        if (blockIdx.x == 0) {
+            st->omega = omega;
+            st->iter = k + 1;
+        }
+    }
+}
+
+struct Bi {
+    Cg<double> c;   // matrix, x, b, r, partials; its CgState holds residual norms
+    double *rh, *p, *v, *y, *s, *z, *t;
+    BiState* st;
+    BiState* h;
+};
+
+int bi_read(Bi& q) {
+    RP_HIP_TRY(hipMemcpyAsync(q.h, q.st, sizeof(BiState), hipMemcpyDeviceToHost, q.c.s));
+    RP_HIP_TRY(hipStreamSynchronize(q.c.s));
+    return RP_OK;
+}
+
+// r = b - A x (x cleared first when xzero) and a (re)start at iteration k
+int bi_launch_start(Bi& q, bool xzero, int32_t k, double tol2) {
+    Cg<double>& c = q.c;
+    RP_TRY((launch_residual<double, false>(c, xzero, nullptr)));
+    hipLaunchKernelGGL(bi_start, dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, k, c.r, q.rh, q.p, q.v, c.part,
+                       q.st);
+    hipLaunchKernelGGL(bi_finalize, dim3(1), dim3(VEC_BLOCK), 0, c.s, 1, k, tol2, c.g_spmv, c.part, q.st);
+    RP_HIP_TRY(hipGetLastError());
+    return bi_read(q);
+}
+
+// rr_true of the current x (r is overwritten)
+int bi_true_residual(Bi& q) {
+    Cg<double>& c = q.c;
+    RP_TRY((launch_residual<double, false>(c, false, nullptr)));
+    hipLaunchKernelGGL(bi_finalize, dim3(1), dim3(VEC_BLOCK), 0, c.s, 0, 0, 0.0, c.g_spmv, c.part, q.st);
+    RP_HIP_TRY(hipGetLastError());
+    return bi_read(q);
+}
+
+int bi_iterate(Bi& q, int chunk, int32_t max_iter) {
+    Cg<double>& c = q.c;
+    const dim3 gs(c.g_spmv), bs(SPMV_BLOCK), gv(c.g_vec), bv(VEC_BLOCK);
+    while (q.h->done == CG_RUNNING && q.h->iter < max_iter) {
+        const int32_t k0 = q.h->iter;
+        const int32_t k1 = (int32_t)std::min<int64_t>((int64_t)k0 + chunk, max_iter);
+        for (int32_t k = k0; k < k1; ++k) {
+            hipLaunchKernelGGL(bi_direction, gv, bv, 0, c.s, c.n, k, c.g_vec, c.r, c.dinv, q.p, q.v, q.y, c.part,
+                               q.st);
+#define RP_LAUNCH(NW)                                                                                        \
+    hipLaunchKernelGGL((bi_spmv_rv<NW>), gs, bs, 0, c.s, c.n, c.ix, c.val, q.y, q.v, q.rh, c.part, q.st, c.w)
+            RP_DISPATCH_NW(c.xw_mode, RP_LAUNCH);
+#undef RP_LAUNCH
+            hipLaunchKernelGGL(bi_half, gv, bv, 0, c.s, c.n, k, c.g_spmv, c.r, q.v, c.dinv, q.s, q.z, c.part, q.st);
+#define RP_LAUNCH(NW)                                                                                         \
+    hipLaunchKernelGGL((bi_spmv_ts<NW>), gs, bs, 0, c.s, c.n, c.g_vec, c.ix, c.val, q.z, q.t, q.s, c.part, q.st, \
+                       c.w)
+            RP_DISPATCH_NW(c.xw_mode, RP_LAUNCH);
+#undef RP_LAUNCH
+            hipLaunchKernelGGL(bi_update, gv, bv, 0, c.s, c.n, k, c.g_spmv, c.x, q.y, q.z, q.s, q.t, q.rh, c.r,
+                               c.part, q.st);
+        }
+        RP_HIP_TRY(hipGetLastError());
+        RP_TRY(bi_read(q));
+    }
+    return RP_OK;
+}
+
+}  // namespace
+
+int solve_bicgstab(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
+                   hipStream_t s) {
+    RP_TRY(check_solvable(p, s, false));
+    const int64_t n = p->n_rows;
+    if (!p->d_bi_work) RP_HIP_TRY(hipMalloc(&p->d_bi_work, sizeof(double) * 5 * (size_t)n));
+    Bi q{make_cg<double>(p, p->d_val64, p->d_dinv64, x, b, p->d_r, p->d_p, p->d_q, p->d_st64, p->h_st64,
+                         RP_KERNEL_SPMV64, s),
+         p->d_bi_work, p->d_p, p->d_q, p->d_bi_work + n, p->d_bi_work + 2 * n, p->d_bi_work + 3 * n,
+         p->d_bi_work + 4 * n, p->d_bi_st, p->h_bi_st};
+    const double tol2 = o.tol * o.tol;
+    const int chunk = std::max(1, o.check_every);
+    RP_TRY(bi_launch_start(q, o.x0_zero != 0, 0, tol2));
+    bool fresh = true;  // rr_true belongs to the current x
+    int status = RP_NOT_CONVERGED;
+    info.restarts = 0;
+    for (;;) {
+        const int32_t d = q.h->done;
+        if (d == CG_ZERO_RHS) {
+            hipLaunchKernelGGL(fill_zero, dim3(q.c.g_vec), dim3(VEC_BLOCK), 0, s, q.c.n, x);
+            RP_HIP_TRY(hipGetLastError());
+            status = RP_OK;
+            break;
+        }
+        if (d == CG_CONVERGED) {
+            if (!fresh) {
+                RP_TRY(bi_true_residual(q));
+                fresh = true;
+            }
+            if (q.h->rr_true <= q.h->thresh) {
+                status = RP_OK;
+                break;
+            }
+            if (info.restarts >= o.max_restarts) break;
+            ++info.restarts;
+            RP_TRY(bi_launch_start(q, false, q.h->iter, tol2));
+            continue;
+        }
+        if (d == CG_BREAKDOWN) {
+            status = RP_ERR_BREAKDOWN;
+            set_error("BiCGStab breakdown after %d iterations", q.h->iter);
+            break;
+        }
+        if (q.h->iter >= o.max_iter) break;
+        RP_TRY(bi_iterate(q, chunk, o.max_iter));
+        fresh = false;
+    }
+    if (!fresh && q.h->done != CG_ZERO_RHS) RP_TRY(bi_true_residual(q));
+    info.iters = q.h->iter;
+    info.outer_iters = 0;
+    info.rel_res = q.h->bb > 0 ? std::sqrt(q.h->rr_true / q.h->bb) : 0.0;
+    info.status = status;
+    if (status == RP_NOT_CONVERGED)
+        set_error("not converged: %d iterations, relative residual %g", info.iters, info.rel_res);
     return status;
 }
 

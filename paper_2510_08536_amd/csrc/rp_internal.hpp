@@ -60,6 +60,7 @@ enum : int32_t {
     CG_BREAKDOWN = 2,   // p.Ap <= 0, (r, z) <= 0 or not finite
     CG_ZERO_RHS = 4,    // ||b|| = 0
     CG_PAUSED = 5,      // residual fell below pause_thresh: FP64 update due
+    BI_HALF = 6,        // BiCGStab: ||s|| small at the half step, x += alpha y due
 };
 
 template <typename S>
@@ -75,6 +76,18 @@ struct CgState {
     S pause_thresh; // pause_frac2 * rr_ref
     int32_t iter;   // completed iterations
     int32_t done;   // CG_*
+};
+
+// Device-side scalars of one BiCGStab solve (FP64)
+struct BiState {
+    double rho[4];  // rho[k & 3] = (rh, r_k), written by iteration k
+    double alpha, omega;
+    double rr;      // (r, r) of the latest residual
+    double bb;      // (b, b)
+    double thresh;  // tol^2 * bb
+    double rr_true; // (r, r) of the last explicit residual b - A x
+    int32_t iter;   // completed iterations
+    int32_t done;   // CG_* / BI_HALF
 };
 
 // partial-sum regions of plan->d_partials (counted in elements of S)
@@ -152,6 +165,9 @@ struct rp_plan {
     rp::CgState<double>* h_st64 = nullptr;   // pinned mirrors
     rp::CgState<float>* h_st32 = nullptr;
     rp::CgState<double>* h_st_outer = nullptr;
+    rp::BiState* d_bi_st = nullptr;          // BiCGStab state and its pinned mirror
+    rp::BiState* h_bi_st = nullptr;
+    double* d_bi_work = nullptr;             // [5 n_rows] BiCGStab vectors rh, y, s, z, t (first use)
     uint32_t* d_flags = nullptr;     // [2] error bits, asymmetry flag
     uint32_t* h_flags = nullptr;     // pinned mirror
 
@@ -215,6 +231,8 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
                hipStream_t s);
 // reliable = true: FP32 PCG with FP64 residual replacement (RP_MIXED);
 // false: restarted FP32 inner PCG under FP64 refinement (RP_MIXED_IR)
+int solve_bicgstab(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
+                   hipStream_t s);
 int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
                 hipStream_t s, bool reliable);
 // grad.hip

@@ -36,6 +36,7 @@ RP_ERR_UNSUPPORTED = -5
 RP_ERR_BREAKDOWN = -6
 RP_ERR_VALUE = -7
 RP_FP64, RP_MIXED, RP_FP32, RP_MIXED_IR = 0, 1, 2, 3
+RP_CG, RP_BICGSTAB = 0, 1
 RP_KERNEL_SPMV64, RP_KERNEL_SPMV32, RP_KERNEL_SCATTER = 0, 1, 2
 
 STATUS_NAMES = {0: "RP_OK", 1: "RP_NOT_CONVERGED", -1: "RP_ERR_ARG", -2: "RP_ERR_MESH",
@@ -59,7 +60,7 @@ class rp_rank_desc(C.Structure):
 class rp_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("inner_tol", C.c_double), ("update_delta", C.c_double), ("max_iter", C.c_int32),
                 ("precision", C.c_int32), ("max_outer", C.c_int32), ("check_every", C.c_int32),
-                ("x0_zero", C.c_int32), ("max_restarts", C.c_int32)]
+                ("x0_zero", C.c_int32), ("max_restarts", C.c_int32), ("method", C.c_int32)]
 
 
 class rp_solve_info(C.Structure):
@@ -157,6 +158,8 @@ def default_opts(**kw) -> rp_solve_opts:
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = {"fp64": RP_FP64, "mixed": RP_MIXED, "mixed_ir": RP_MIXED_IR}[v]
+        if k == "method" and isinstance(v, str):
+            v = {"cg": RP_CG, "bicgstab": RP_BICGSTAB}[v]
         setattr(o, k, v)
     return o
 

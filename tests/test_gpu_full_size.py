@@ -117,6 +117,40 @@ def test_c3_fp64_and_mixed():
     print(f"c3: fp64 {i64['iters']} it, mixed {im['iters']} inner / {im['outer_iters']} outer, "
           f"rel diff {diff:.2e}")
     assert diff <= 1e-2
+    # the same plan refreshed with non-symmetric momentum-type values:
+    # update bit-exact, BiCGStab to a true residual of 1e-8
+    del val64
+    gc.collect()
+    mv = share_values(w, values=w.momentum_values())
+    want = oracle.update(m, oracle.receive_buffer(mv))
+    update(plan, mv, lower=True)
+    del mv
+    _check_plan_and_update(plan, m, want)
+    xb, ib = plan.solve(dev_tensor(b), tol=1e-8, method="bicgstab")
+    rr = oracle.true_relres(m, want[0], b, xb.cpu().numpy())
+    print(f"c3 momentum: bicgstab {ib['iters']} it, true rel.res {rr:.2e}")
+    assert ib["status"] == 0 and rr <= 1e-8
+    plan.close()
+
+
+@pytest.mark.timeout(300)
+def test_c2_momentum_bicgstab():
+    """128^3, 32 ranks, non-symmetric momentum-type values: BiCGStab against
+    the oracle's BiCGStab."""
+    w = synth.build("c2")
+    m = oracle.merge(w.part.n_cells, 0, w.n_ranks, share_ranks(w))
+    mv = share_values(w, values=w.momentum_values())
+    want = oracle.update(m, oracle.receive_buffer(mv))
+    plan = make_plan(w)
+    update(plan, mv, lower=True)
+    _check_plan_and_update(plan, m, want)
+    b = w.rhs()
+    x, info = plan.solve(dev_tensor(b), tol=1e-8, method="bicgstab")
+    xh = x.cpu().numpy()
+    assert info["status"] == 0 and oracle.true_relres(m, want[0], b, xh) <= 1e-8
+    x_or, st, it_or, _, _ = oracle.bicgstab(m, want[0], b, tol=1e-8)
+    assert st == 0 and np.linalg.norm(xh - x_or) <= 1e-6 * np.linalg.norm(x_or)
+    assert abs(info["iters"] - it_or) <= max(3, int(0.1 * it_or)), (info["iters"], it_or)
     plan.close()
 
 
