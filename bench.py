@@ -12,6 +12,8 @@ One step = one timestep of the whole path:
   FP64 PCG   A x = b from x = 0 to ||b - A x|| <= 1e-8 ||b||
   mixed      FP32 inner PCG under FP64 refinement, same b, x = 0, same target
   adjoint    lambda = A^-1 (x - x_t) (FP64 PCG) and the slot gradient
+  momentum   the plan refreshed with a non-symmetric convection-diffusion
+             system on the same ranks, solved with BiCGStab (FP64, 1e-8)
 The plan (pattern, U, P) is built once before the steps and timed apart.
 
 Prints one JSON line.  value = median ms per FP64 pressure solve; the mixed
@@ -120,6 +122,14 @@ def main():
         steps_vals.append(([to_dev(v.diag[p.cell_ptr[r]:p.cell_ptr[r + 1]]) for r in range(w.n_ranks)],
                            [to_dev(v.upper[p.face_ptr[r]:p.face_ptr[r + 1]]) for r in range(w.n_ranks)],
                            [to_dev(v.iface[p.if_ptr[r]:p.if_ptr[r + 1]]) for r in range(w.n_ranks)]))
+    # the non-symmetric momentum-type system on the same ranks (one set of
+    # values, refreshed into the plan every step)
+    vm = w.momentum_values()
+    mom_vals = ([to_dev(vm.diag[p.cell_ptr[r]:p.cell_ptr[r + 1]]) for r in range(w.n_ranks)],
+                [to_dev(vm.upper[p.face_ptr[r]:p.face_ptr[r + 1]]) for r in range(w.n_ranks)],
+                [to_dev(vm.iface[p.if_ptr[r]:p.if_ptr[r + 1]]) for r in range(w.n_ranks)],
+                [to_dev(vm.lower[p.face_ptr[r]:p.face_ptr[r + 1]]) for r in range(w.n_ranks)])
+    del vm
     b = to_dev(w.rhs())
     xt = to_dev(w.target())
     print(f"[bench] {n_steps_total} timesteps of values resident in HBM", flush=True)
@@ -147,6 +157,7 @@ def main():
 
     o64 = lambda: default_opts(tol=1e-8, precision="fp64", x0_zero=1)
     omx = lambda: default_opts(tol=1e-8, precision="mixed", x0_zero=1)
+    obi = lambda: default_opts(tol=1e-8, precision="fp64", method="bicgstab", x0_zero=1)
     stream = torch.cuda.current_stream()
 
     def ev():
@@ -166,10 +177,14 @@ def main():
         lam, infl = plan.solve(x64 - xt, opts=o64())
         g = plan.value_grad(lam, x64)
         e4 = ev()
+        plan.update(mom_vals[0], mom_vals[1], mom_vals[2], lower=mom_vals[3])
+        e5 = ev()
+        xbi, infbi = plan.solve(b, opts=obi())
+        e6 = ev()
         if rec is not None:
-            rec.append(dict(ev=(e0, e1, e2, e3, e4), fp64=inf64, mixed=infmx, adj=infl,
+            rec.append(dict(ev=(e0, e1, e2, e3, e4, e5, e6), fp64=inf64, mixed=infmx, adj=infl, bicg=infbi,
                             x64=x64, xmx=xmx))
-        for info in (inf64, infmx, infl):
+        for info in (inf64, infmx, infl, infbi):
             assert info["status"] == 0 and info["rel_res"] <= 1e-8, info
         return g
 
@@ -198,6 +213,9 @@ def main():
     f64 = [el(r["ev"][1], r["ev"][2]) for r in recs]
     mx = [el(r["ev"][2], r["ev"][3]) for r in recs]
     adj = [el(r["ev"][3], r["ev"][4]) for r in recs]
+    mupd = [el(r["ev"][4], r["ev"][5]) for r in recs]
+    bic = [el(r["ev"][5], r["ev"][6]) for r in recs]
+    itbi = [r["bicg"]["iters"] for r in recs]
     it64 = [r["fp64"]["iters"] for r in recs]
     itmx = [r["mixed"]["iters"] for r in recs]
     last = recs[-1]
@@ -212,6 +230,8 @@ def main():
     spmv32_bytes = 8 * nnz + 12 * n + 4
     iter64_bytes = 12 * nnz + 108 * n
     iter32_bytes = 8 * nnz + 56 * n
+    # BiCGStab iteration: two CSR SpMVs plus 168 n of vectors (p, y, v, rh, s, z, t, x, r)
+    iterbi_bytes = 2 * (12 * nnz + 20 * n) + 168 * n
     kern64_bytes = fmt["bytes64"]            # what the SpMV kernels read and write in the form in use
     kern32_bytes = fmt["bytes32"]
     spmv_avg_ms = ms_spmv / max(n_spmv, 1)
@@ -235,7 +255,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.config}: {w.recipe.note}", "n_rows": n, "nnz": nnz, "alpha": w.n_ranks,
                    "tol": 1e-8, "x0": "zero",
-                   "step": "update + FP64 PCG + mixed PCG + adjoint (lambda solve + slot gradient)"},
+                   "step": "update + FP64 PCG + mixed PCG + adjoint (lambda solve + slot gradient) + "
+                           "momentum update + BiCGStab"},
         "fp64": {"ms_per_solve": round(med(f64), 3), "iters": int(np.median(it64)),
                  "ms_per_iter": round(med(f64) / max(np.median(it64), 1), 4),
                  "iter_GBps_alg": round(iter64_bytes * np.median(it64) / (med(f64) * 1e-3) / 1e9, 1)},
@@ -244,6 +265,10 @@ def main():
                   "speedup_vs_fp64": round(med(f64) / med(mx), 3),
                   "rel_diff_vs_fp64_solution": diff,
                   "inner_iter_GBps_alg": round(iter32_bytes * np.median(itmx) / (med(mx) * 1e-3) / 1e9, 1)},
+        "momentum_bicgstab": {"ms_per_solve": round(med(bic), 3), "iters": int(np.median(itbi)),
+                              "ms_per_iter": round(med(bic) / max(np.median(itbi), 1), 4),
+                              "iter_GBps_alg": round(iterbi_bytes * np.median(itbi) / (med(bic) * 1e-3) / 1e9, 1),
+                              "update_ms": round(med(mupd), 3)},
         "adjoint_ms": round(med(adj), 3),
         "adjoint_iters": int(np.median([r["adj"]["iters"] for r in recs])),
         "update_ms": round(med(upd), 3),
