@@ -302,7 +302,7 @@ def main():
 def cpu_baseline(w, iters, gpu_ms, gpu_iters, t_last, x_gpu):
     """The oracle (serial C, one thread) on the same system: merge and update
     timed in full, PCG timed over `iters` iterations and scaled to the GPU
-    solve's iteration count.  Also judges the last timed FP64 GPU solution
+    solve's iteration count.  Also checks the last timed FP64 GPU solution
     with the oracle's own residual."""
     import oracle
     ranks = [w.part.rank(r) for r in range(w.n_ranks)]

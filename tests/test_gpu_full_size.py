@@ -2,7 +2,7 @@
 benchmark times.
 
 Pattern, permutation and values are compared with the oracle in full (bit
-for bit).  Solves are judged by the true relative residual the oracle's own
+for bit).  Solves are checked by the true relative residual the oracle's own
 SpMV computes for the GPU answer (<= 1e-8) and, where the oracle's serial
 solve fits in the test (32^3, 128^3, 96^3), by the error against the oracle's
 solution.  For the 256^3 and 160^3 systems (condition numbers far above the
