@@ -3,7 +3,8 @@
 forward:  update the plan with the slot values, solve A x = b (FP64 PCG or
           mixed refinement), keep x (not the Krylov history).
 backward: lambda = A^-T dL/dx by one more solve (A is symmetric, so the same
-          matrix and kernels), dL/db = lambda, and the slot gradient
+          matrix and kernels; a non-symmetric solve is refused, since its
+          adjoint would need A^T), dL/db = lambda, and the slot gradient
           dL/dv_k = -lambda[row(k)] x[col(k)] from rp_value_grad, returned in
           receive-buffer order.  The caller's own assembly (face coefficient ->
           slot values) chains these to its parameters through torch.
@@ -12,15 +13,19 @@ from __future__ import annotations
 
 import torch
 
-from .rp import Plan, default_opts
+from .rp import Plan, RP_CG, default_opts, rp_solve_opts
 
 
 class RepartSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, slot_values: torch.Tensor, b: torch.Tensor, plan: Plan, opts=None):
         slot_values = slot_values.contiguous()
-        plan.update_slots(slot_values)
         o = opts if opts is not None else default_opts()
+        if o.method != RP_CG:
+            raise ValueError("RepartSolve differentiates the symmetric (CG) solve; the adjoint of a "
+                             "non-symmetric solve would need A^T")
+        o = rp_solve_opts.from_buffer_copy(o)     # the caller's options stay untouched
+        plan.update_slots(slot_values)
         x, info = plan.solve(b.contiguous(), opts=o)
         ctx.plan = plan
         ctx.version = plan.version
@@ -36,7 +41,7 @@ class RepartSolve(torch.autograd.Function):
         if plan.version != ctx.version:
             # the plan was refreshed with other values since the forward pass
             plan.update_slots(slot_values)
-        o = ctx.opts
+        o = rp_solve_opts.from_buffer_copy(ctx.opts)
         o.x0_zero = 1
         lam, _ = plan.solve(gx.contiguous(), opts=o)
         g_slots = plan.value_grad(lam, x) if ctx.needs_input_grad[0] else None

@@ -140,3 +140,24 @@ def test_backward_after_other_update_uses_saved_values():
     gc = c.grad.cpu().numpy()
     assert np.max(np.abs(gc - g_or) / np.maximum(1.0, np.abs(g_or))) <= 1e-6
     plan.close()
+
+
+def test_autograd_refuses_nonsymmetric_method_and_keeps_caller_opts():
+    """The Function differentiates the CG (symmetric) solve only, and works on
+    a copy of the caller's options."""
+    torch = torch_mod()
+    from paper_2510_08536_amd import default_opts
+    from paper_2510_08536_amd.autograd import repart_solve
+    w = synth.small((6, 5, 4), ("blocks", 2, 1, 1), kappa=(1e-2, 1.0), seed=77)
+    plan = make_plan(w)
+    asm = Assembly(w, plan)
+    c = torch.as_tensor(w.coefficients(), device="cuda:0").requires_grad_(True)
+    b = dev_tensor(w.rhs())
+    with pytest.raises(ValueError):
+        repart_solve(asm(c), b, plan, default_opts(method="bicgstab"))
+    o = default_opts(tol=1e-10)
+    assert o.x0_zero == 0
+    x = repart_solve(asm(c), b, plan, o)
+    (0.5 * (x * x).sum()).backward()
+    assert o.x0_zero == 0 and c.grad is not None and torch.isfinite(c.grad).all()
+    plan.close()
