@@ -105,6 +105,8 @@ typedef struct rp_solve_opts {
     int32_t max_restarts;    /* FP64: restarts when the recurrence residual passes
                                 but the true residual does not (default 5) */
     int32_t method;          /* RP_CG (default) or RP_BICGSTAB */
+    int32_t transpose;       /* 1: solve A^T x = b (the adjoint solve); with RP_CG, where A
+                                is symmetric, this is the same system (default 0) */
 } rp_solve_opts;
 
 typedef struct rp_solve_info {
@@ -218,7 +220,10 @@ int rp_spmv(rp_plan* plan, int32_t precision, const void* x, void* y, void* stre
  * opts->method = RP_BICGSTAB: BiCGStab with M = diag(A) applied on the
  * right, in FP64, for non-symmetric matrices (van der Vorst 1992; one
  * iteration = two products with A); its stop test and restart follow the
- * CG's.  b, x: device arrays of n_rows doubles in fused row order (the share's
+ * CG's.  opts->transpose = 1 solves A^T x = b: A's values are gathered into
+ * A^T's (the fused pattern is structurally symmetric, so every entry (i, j)
+ * has a partner (j, i)) whenever they changed since the last such solve.
+ * b, x: device arrays of n_rows doubles in fused row order (the share's
  * ranks in order, each in local cell order).  x holds x0 on entry (unless
  * opts->x0_zero) and the solution on return.  opts NULL = defaults.  Blocks
  * until the solve is finished.  Returns RP_OK, RP_NOT_CONVERGED,

@@ -2,9 +2,10 @@
 
 forward:  update the plan with the slot values, solve A x = b (FP64 PCG or
           mixed refinement), keep x (not the Krylov history).
-backward: lambda = A^-T dL/dx by one more solve (A is symmetric, so the same
-          matrix and kernels; a non-symmetric solve is refused, since its
-          adjoint would need A^T), dL/db = lambda, and the slot gradient
+backward: lambda = A^-T dL/dx by one more solve (opts.transpose = 1: with CG,
+          A is symmetric and this is the same system; with BiCGStab the
+          library gathers A^T's values on the same pattern), dL/db = lambda,
+          and the slot gradient
           dL/dv_k = -lambda[row(k)] x[col(k)] from rp_value_grad, returned in
           receive-buffer order.  The caller's own assembly (face coefficient ->
           slot values) chains these to its parameters through torch.
@@ -13,7 +14,7 @@ from __future__ import annotations
 
 import torch
 
-from .rp import Plan, RP_CG, default_opts, rp_solve_opts
+from .rp import Plan, default_opts, rp_solve_opts
 
 
 class RepartSolve(torch.autograd.Function):
@@ -21,10 +22,8 @@ class RepartSolve(torch.autograd.Function):
     def forward(ctx, slot_values: torch.Tensor, b: torch.Tensor, plan: Plan, opts=None):
         slot_values = slot_values.contiguous()
         o = opts if opts is not None else default_opts()
-        if o.method != RP_CG:
-            raise ValueError("RepartSolve differentiates the symmetric (CG) solve; the adjoint of a "
-                             "non-symmetric solve would need A^T")
         o = rp_solve_opts.from_buffer_copy(o)     # the caller's options stay untouched
+        o.transpose = 0
         plan.update_slots(slot_values)
         x, info = plan.solve(b.contiguous(), opts=o)
         ctx.plan = plan
@@ -43,6 +42,7 @@ class RepartSolve(torch.autograd.Function):
             plan.update_slots(slot_values)
         o = rp_solve_opts.from_buffer_copy(ctx.opts)
         o.x0_zero = 1
+        o.transpose = 1
         lam, _ = plan.solve(gx.contiguous(), opts=o)
         g_slots = plan.value_grad(lam, x) if ctx.needs_input_grad[0] else None
         g_b = lam if ctx.needs_input_grad[1] else None

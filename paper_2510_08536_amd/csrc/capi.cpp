@@ -75,7 +75,8 @@ void free_plan(rp_plan* p) {
                    p->d_perm, p->d_perm_inv, p->d_nl_row_ptr, p->d_nl_col, p->d_iface_partner, p->d_recv,
                    p->d_val64, p->d_val32, p->d_dinv64, p->d_dinv32, p->d_r, p->d_p, p->d_q, p->d_r32,
                    p->d_p32, p->d_q32, p->d_x32, p->d_partials, p->d_st64, p->d_st32, p->d_st_outer,
-                   p->d_flags, p->d_goi_k, p->d_goi_off, p->d_goi_mask, p->d_bi_st, p->d_bi_work};
+                   p->d_flags, p->d_goi_k, p->d_goi_off, p->d_goi_mask, p->d_bi_st, p->d_bi_work,
+                   p->d_valT, p->d_tflag};
     for (void* q : dev)
         if (q) (void)hipFree(q);
     if (p->h_st64) (void)hipHostFree(p->h_st64);
@@ -250,6 +251,7 @@ int update(rp_plan* p, const double* const* diag, const double* const* upper, co
     RP_TRY(launch_symmetry_check(p, p->d_recv, lower != nullptr, s));
     RP_TRY(launch_update(p, p->d_recv, s));
     p->has_values = true;
+    p->values_version += 1;
     p->last_stream = s;
     return RP_OK;
 }
@@ -386,6 +388,7 @@ int rp_update_values_slots(rp_plan* p, const double* slots, void* stream) {
     RP_TRY(launch_symmetry_check(p, slots, true, s));
     RP_TRY(launch_update(p, slots, s));
     p->has_values = true;
+    p->values_version += 1;
     p->last_stream = s;
     return RP_OK;
 }
@@ -414,6 +417,7 @@ void rp_solve_opts_default(rp_solve_opts* o) {
     o->x0_zero = 0;
     o->max_restarts = 5;
     o->method = RP_CG;
+    o->transpose = 0;
 }
 
 int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, rp_solve_info* info,
@@ -435,6 +439,7 @@ int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, 
              "precision must be RP_FP64, RP_MIXED or RP_MIXED_IR");
     RP_CHECK(o.method == RP_CG || o.method == RP_BICGSTAB, RP_ERR_ARG, "method must be RP_CG or RP_BICGSTAB");
     RP_CHECK(o.method == RP_CG || o.precision == RP_FP64, RP_ERR_UNSUPPORTED, "BiCGStab runs in FP64 only");
+    RP_CHECK(o.transpose == 0 || o.transpose == 1, RP_ERR_ARG, "transpose must be 0 or 1");
     RP_TRY(activate(p));
     hipStream_t s = as_stream(stream);
     p->last_stream = s;

@@ -881,7 +881,10 @@ int solve_bicgstab(rp_plan* p, const double* b, double* x, const rp_solve_opts& 
     RP_TRY(check_solvable(p, s, false));
     const int64_t n = p->n_rows;
     if (!p->d_bi_work) RP_HIP_TRY(hipMalloc(&p->d_bi_work, sizeof(double) * 5 * (size_t)n));
-    Bi q{make_cg<double>(p, p->d_val64, p->d_dinv64, x, b, p->d_r, p->d_p, p->d_q, p->d_st64, p->h_st64,
+    // A^T x = b: same pattern and diagonal, transposed values
+    if (o.transpose) RP_TRY(build_transpose(p, s));
+    const double* val = o.transpose ? p->d_valT : p->d_val64;
+    Bi q{make_cg<double>(p, val, p->d_dinv64, x, b, p->d_r, p->d_p, p->d_q, p->d_st64, p->h_st64,
                          RP_KERNEL_SPMV64, s),
          p->d_bi_work, p->d_p, p->d_q, p->d_bi_work + n, p->d_bi_work + 2 * n, p->d_bi_work + 3 * n,
          p->d_bi_work + 4 * n, p->d_bi_st, p->h_bi_st};

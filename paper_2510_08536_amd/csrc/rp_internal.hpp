@@ -150,6 +150,10 @@ struct rp_plan {
     double* d_dinv64 = nullptr;      // [n_rows]
     float* d_dinv32 = nullptr;       // [n_rows]
     bool has_values = false;
+    int64_t values_version = 0;      // bumped by every update
+    double* d_valT = nullptr;        // [nnz + SPMV_PAD] values of A^T (first transposed solve)
+    int64_t valT_version = -1;       // values_version d_valT was built from
+    uint32_t* d_tflag = nullptr;     // set when an entry has no transposed partner
 
     // staging table for device-resident per-rank values: 4*alpha pointers
     const double** d_src = nullptr;
@@ -233,6 +237,7 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
 // false: restarted FP32 inner PCG under FP64 refinement (RP_MIXED_IR)
 int solve_bicgstab(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
                    hipStream_t s);
+int build_transpose(rp_plan* p, hipStream_t s);
 int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
                 hipStream_t s, bool reliable);
 // grad.hip

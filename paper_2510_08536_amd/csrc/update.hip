@@ -7,6 +7,7 @@
 // same pass writes the FP32 copy (round to nearest even) and flags values
 // that are not finite; a second grid part computes the Jacobi inverse
 // diagonal as one IEEE division per row.
+#include <algorithm>
 #include <cmath>
 
 #include "device_util.hpp"
@@ -109,7 +110,57 @@ int grid_for(int64_t n, int block = 256, int cap = 8192) {
     return (int)g;
 }
 
+// Values of A^T on the fused pattern: entry (i, j) takes A(j, i), found by a
+// binary search for column i in row j (columns ascend within a row).  An
+// entry without a partner sets *missing.
+__global__ void transpose_values(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                 const double* __restrict__ val, double* __restrict__ valT,
+                                 uint32_t* __restrict__ missing) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const int32_t j = col[e];
+            int32_t a = row_ptr[j], b = row_ptr[j + 1];
+            while (a < b) {
+                const int32_t m = (a + b) >> 1;
+                if (col[m] < i) a = m + 1;
+                else b = m;
+            }
+            if (a < row_ptr[j + 1] && col[a] == i) {
+                valT[e] = val[a];
+            } else {
+                valT[e] = 0.0;
+                atomicOr(missing, 1u);
+            }
+        }
+    }
+}
+
 }  // namespace
+
+// A^T's values into d_valT, unless they are current (same values_version)
+int build_transpose(rp_plan* p, hipStream_t s) {
+    if (p->d_valT != nullptr && p->valT_version == p->values_version) return RP_OK;
+    if (p->d_valT == nullptr) {
+        RP_HIP_TRY(hipMalloc(&p->d_valT, sizeof(double) * ((size_t)p->nnz + SPMV_PAD)));
+        RP_HIP_TRY(hipMemsetAsync(p->d_valT + p->nnz, 0, sizeof(double) * SPMV_PAD, s));
+        RP_HIP_TRY(hipMalloc(&p->d_tflag, sizeof(uint32_t)));
+    }
+    RP_HIP_TRY(hipMemsetAsync(p->d_tflag, 0, sizeof(uint32_t), s));
+    const int32_t n = (int32_t)p->n_rows;
+    const int grid = (int)std::min<int64_t>((p->n_rows + 255) / 256, 4096);
+    hipLaunchKernelGGL(transpose_values, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, n, p->d_row_ptr, p->d_col,
+                       p->d_val64, p->d_valT, p->d_tflag);
+    RP_HIP_TRY(hipGetLastError());
+    uint32_t missing = 0;
+    RP_HIP_TRY(hipMemcpyAsync(&missing, p->d_tflag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    RP_HIP_TRY(hipStreamSynchronize(s));
+    if (missing) {
+        set_error("the fused pattern is not structurally symmetric: A^T has entries outside it");
+        return RP_ERR_UNSUPPORTED;
+    }
+    p->valT_version = p->values_version;
+    return RP_OK;
+}
 
 int launch_stage_table(rp_plan* p, bool lower_given, hipStream_t s) {
     for (int32_t s0 = 0; s0 < p->alpha; s0 += STAGE_RANKS) {

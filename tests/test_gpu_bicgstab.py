@@ -147,3 +147,39 @@ def test_bicgstab_strong_convection():
     x_or, st, it_or, _, _ = oracle.bicgstab(m, val64, b, tol=1e-8)
     assert st == 0 and np.linalg.norm(xh - x_or) <= 1e-6 * np.linalg.norm(x_or)
     plan.close()
+
+
+def test_bicgstab_transposed_solve_matches_oracle():
+    """opts.transpose = 1 solves A^T x = b; the oracle solves the explicitly
+    transposed CSR (scipy's transpose of the oracle's matrix)."""
+    import scipy.sparse as sp
+    w, m, val64, plan = _setup("rcb_mixed", pe=6.0)
+    AT = sp.csr_matrix((val64, m.col, m.row_ptr), shape=(m.n_rows, m.n_rows)).T.tocsr()
+    AT.sort_indices()
+    g = np.random.default_rng(8).uniform(-1, 1, m.n_rows)
+    lam_or, st, it_or, _, _ = oracle.bicgstab_csr(AT.indptr, AT.indices, AT.data, g, tol=1e-8)
+    assert st == 0
+    lam, info = plan.solve(dev_tensor(g), tol=1e-8, method="bicgstab", transpose=1)
+    lh = lam.cpu().numpy()
+    rr = np.linalg.norm(g - AT @ lh) / np.linalg.norm(g)
+    assert info["status"] == 0 and rr <= 1e-8 * (1 + 1e-6), rr
+    assert np.linalg.norm(lh - lam_or) <= 1e-6 * np.linalg.norm(lam_or)
+    # A and A^T differ here, so the untransposed answer must not solve A^T
+    x, _ = plan.solve(dev_tensor(g), tol=1e-8, method="bicgstab")
+    assert np.linalg.norm(g - AT @ x.cpu().numpy()) / np.linalg.norm(g) > 1e-4
+    plan.close()
+
+
+def test_transpose_of_symmetric_values_is_the_same_solve():
+    """On symmetric values the gathered A^T equals A bit for bit, so the
+    transposed BiCGStab solve is bit-identical; CG ignores the flag."""
+    torch = torch_mod()
+    w = CASES["blocks"]()
+    plan = make_plan(w)
+    update(plan, share_values(w))
+    b = dev_tensor(w.rhs())
+    for method in ("bicgstab", "cg"):
+        x0, i0 = plan.solve(b, tol=1e-8, method=method)
+        x1, i1 = plan.solve(b, tol=1e-8, method=method, transpose=1)
+        assert i0["iters"] == i1["iters"] and torch.equal(x0, x1), method
+    plan.close()
