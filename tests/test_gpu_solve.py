@@ -256,3 +256,23 @@ def test_kernel_timing_counts_iterations():
     assert n32 == info["iters"]
     plan.set_timing(False)
     plan.close()
+
+
+def test_update_and_solve_on_a_side_stream():
+    """The library enqueues on the stream it is given (torch's current one by
+    default): the same update and solve on a second stream give the same
+    bits as on the default stream."""
+    torch = torch_mod()
+    w, m, val64, plan = _setup("c1")
+    b = dev_tensor(w.rhs())
+    x0, i0 = plan.solve(b, tol=1e-8)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        update(plan, share_values(w))
+        x1, i1 = plan.solve(b, tol=1e-8)
+        x2, i2 = plan.solve(b, tol=1e-8, method="bicgstab")
+    side.synchronize()
+    assert i0["iters"] == i1["iters"] and torch.equal(x0, x1)
+    assert i2["status"] == 0 and oracle.true_relres(m, val64, w.rhs(), x2.cpu().numpy()) <= 1e-8
+    plan.close()
