@@ -107,6 +107,13 @@ typedef struct rp_solve_opts {
     int32_t method;          /* RP_CG (default) or RP_BICGSTAB */
     int32_t transpose;       /* 1: solve A^T x = b (the adjoint solve); with RP_CG, where A
                                 is symmetric, this is the same system (default 0) */
+    int32_t graph;           /* RP_CG, 1: launch each check_every-iteration chunk as one
+                                replay of a HIP graph captured on first use and kept in
+                                the plan (captured again when a solve's vectors or chunk
+                                length differ).  Same arithmetic and results as 0; pays
+                                off where launches, not the SpMV, bound an iteration.
+                                Ignored while kernel timing is on and by RP_BICGSTAB
+                                (default 0) */
 } rp_solve_opts;
 
 typedef struct rp_solve_info {

@@ -84,6 +84,9 @@ void free_plan(rp_plan* p) {
     if (p->h_st_outer) (void)hipHostFree(p->h_st_outer);
     if (p->h_bi_st) (void)hipHostFree(p->h_bi_st);
     if (p->h_flags) (void)hipHostFree(p->h_flags);
+    for (auto& g : p->cg_graph)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     for (auto& e : p->timing.pool) {
         for (hipEvent_t ev : e.start) (void)hipEventDestroy(ev);
         for (hipEvent_t ev : e.stop) (void)hipEventDestroy(ev);
@@ -418,6 +421,7 @@ void rp_solve_opts_default(rp_solve_opts* o) {
     o->max_restarts = 5;
     o->method = RP_CG;
     o->transpose = 0;
+    o->graph = 0;
 }
 
 int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, rp_solve_info* info,
@@ -440,6 +444,7 @@ int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, 
     RP_CHECK(o.method == RP_CG || o.method == RP_BICGSTAB, RP_ERR_ARG, "method must be RP_CG or RP_BICGSTAB");
     RP_CHECK(o.method == RP_CG || o.precision == RP_FP64, RP_ERR_UNSUPPORTED, "BiCGStab runs in FP64 only");
     RP_CHECK(o.transpose == 0 || o.transpose == 1, RP_ERR_ARG, "transpose must be 0 or 1");
+    RP_CHECK(o.graph == 0 || o.graph == 1, RP_ERR_ARG, "graph must be 0 or 1");
     RP_TRY(activate(p));
     hipStream_t s = as_stream(stream);
     p->last_stream = s;

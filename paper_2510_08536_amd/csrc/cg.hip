@@ -115,7 +115,7 @@ enum : int32_t { FIN_START = 0, FIN_RESIDUAL = 1 };
 // cg_start_p's (r, z): thresh = tol2 * bb, pause_thresh = pause_frac2 * rr.
 template <typename T>
 __global__ void __launch_bounds__(VEC_BLOCK)
-cg_finalize(int32_t mode, int32_t k, T tol2, T pause_frac2, int32_t g_spmv, int32_t g_vec,
+cg_finalize(int32_t mode, int32_t k, int32_t max_iter, T tol2, T pause_frac2, int32_t g_spmv, int32_t g_vec,
             const T* __restrict__ part, CgState<T>* st) {
 #pragma clang fp contract(off)
     __shared__ T red[VEC_BLOCK / 64];
@@ -135,6 +135,7 @@ cg_finalize(int32_t mode, int32_t k, T tol2, T pause_frac2, int32_t g_spmv, int3
     st->pause_frac2 = pause_frac2;
     st->pause_thresh = pause_frac2 * rr;
     st->iter = k;
+    st->max_iter = max_iter;
     int32_t d = CG_RUNNING;
     if (bb == T(0)) d = CG_ZERO_RHS;
     else if (rr <= thresh) d = CG_CONVERGED;
@@ -148,7 +149,7 @@ __global__ void __launch_bounds__(SPMV_BLOCK)
 cg_spmv_pq(int32_t n, SpmvIdx ix, const T* __restrict__ val, const T* __restrict__ p, T* __restrict__ q,
            T* __restrict__ part, const CgState<T>* st, XWin w) {
 #pragma clang fp contract(off)
-    if (st->done != CG_RUNNING) return;
+    if (st->done != CG_RUNNING || st->iter >= st->max_iter) return;
     __shared__ __align__(16) T lds[SPMV_CAP];
     __shared__ T xs[XWinSize<NW>::value];
     __shared__ T red[SPMV_BLOCK / 64];
@@ -172,10 +173,17 @@ cg_spmv_pq(int32_t n, SpmvIdx ix, const T* __restrict__ val, const T* __restrict
 // PART_RZ and (r, r) -> PART_RR.  x moves in K3, which reads p anyway.
 template <typename T>
 __global__ void __launch_bounds__(VEC_BLOCK)
-cg_update_r(int32_t n, int32_t k, int32_t g_spmv, T* __restrict__ r, const T* __restrict__ q,
+cg_update_r(int32_t n, int32_t k_arg, int32_t g_spmv, T* __restrict__ r, const T* __restrict__ q,
             const T* __restrict__ dinv, T* __restrict__ part, CgState<T>* st) {
 #pragma clang fp contract(off)
     if (st->done != CG_RUNNING) return;
+    // iteration number: the argument, or (replayed graphs) the device state,
+    // which only K3 and the finalize kernel write
+    const int32_t k = k_arg >= 0 ? k_arg : st->iter;
+    if (k >= st->max_iter) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->kk = -1;
+        return;
+    }
     __shared__ T red[VEC_BLOCK / 64];
     const T pq = sum_partials_all<T, VEC_BLOCK>(part + PART_A, g_spmv, red);
     if (!(pq > T(0)) || !isfinite(pq)) {
@@ -203,6 +211,7 @@ cg_update_r(int32_t n, int32_t k, int32_t g_spmv, T* __restrict__ r, const T* __
         if (blockIdx.x == 0) {
             st->pq = pq;
             st->alpha = a;
+            st->kk = k;
         }
     }
 }
@@ -214,11 +223,14 @@ cg_update_r(int32_t n, int32_t k, int32_t g_spmv, T* __restrict__ r, const T* __
 // tests are skipped.
 template <typename T>
 __global__ void __launch_bounds__(VEC_BLOCK)
-cg_update_xp(int32_t n, int32_t k, int32_t g_vec, int32_t resume, const T* __restrict__ r,
+cg_update_xp(int32_t n, int32_t k_arg, int32_t g_vec, int32_t resume, const T* __restrict__ r,
              const T* __restrict__ dinv, T* __restrict__ x, T* __restrict__ p, const T* __restrict__ part,
              CgState<T>* st) {
 #pragma clang fp contract(off)
     if (!resume && st->done != CG_RUNNING) return;
+    // iteration number: the argument, or the one K2 of this iteration wrote
+    const int32_t k = k_arg >= 0 ? k_arg : st->kk;
+    if (k < 0) return;
     __shared__ T red[VEC_BLOCK / 64];
     const T rz = sum_partials_all<T, VEC_BLOCK>(part + PART_RZ, g_vec, red);
     const T rr = sum_partials_all<T, VEC_BLOCK>(part + PART_RR, g_vec, red);
@@ -334,8 +346,8 @@ int launch_residual(Cg<T>& c, bool xzero, float* r32) {
 }
 
 template <typename T>
-int launch_finalize(Cg<T>& c, int32_t mode, int32_t k, T tol2, T pause_frac2) {
-    hipLaunchKernelGGL(cg_finalize<T>, dim3(1), dim3(VEC_BLOCK), 0, c.s, mode, k, tol2, pause_frac2, c.g_spmv,
+int launch_finalize(Cg<T>& c, int32_t mode, int32_t k, T tol2, T pause_frac2, int32_t max_iter = 0) {
+    hipLaunchKernelGGL(cg_finalize<T>, dim3(1), dim3(VEC_BLOCK), 0, c.s, mode, k, max_iter, tol2, pause_frac2, c.g_spmv,
                        c.g_vec, c.part, c.st);
     RP_HIP_TRY(hipGetLastError());
     return RP_OK;
@@ -344,10 +356,10 @@ int launch_finalize(Cg<T>& c, int32_t mode, int32_t k, T tol2, T pause_frac2) {
 // (re)start at iteration k from the residual in r (the residual_kernel's
 // partials are still in PART_A / PART_B)
 template <typename T>
-int launch_start(Cg<T>& c, int32_t k, T tol2, T pause_frac2) {
+int launch_start(Cg<T>& c, int32_t k, T tol2, T pause_frac2, int32_t max_iter) {
     hipLaunchKernelGGL(cg_start_p<T>, dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, c.r, c.dinv, c.p, c.part);
     RP_HIP_TRY(hipGetLastError());
-    return launch_finalize(c, FIN_START, k, tol2, pause_frac2);
+    return launch_finalize(c, FIN_START, k, tol2, pause_frac2, max_iter);
 }
 
 // continue after r was replaced: beta from the new (r, z), p update, running again
@@ -361,29 +373,85 @@ int launch_resume(Cg<T>& c) {
     return RP_OK;
 }
 
-// enqueue chunks of up to `chunk` iterations (never past max_iter) until the
-// state leaves CG_RUNNING or the budget is spent
+// one iteration as K1, K2, K3 on stream s (K1 between the timing events);
+// k < 0: K2 and K3 take the iteration number from the device state (graphs)
 template <typename T>
-int iterate(Cg<T>& c, int chunk, int32_t max_iter) {
+int launch_iteration(Cg<T>& c, int32_t k, hipStream_t s) {
     const dim3 gs(c.g_spmv), bs(SPMV_BLOCK), gv(c.g_vec), bv(VEC_BLOCK);
+    RP_TRY(timing_begin(c.plan, c.kernel_id, s));
+#define RP_LAUNCH(NW) \
+    hipLaunchKernelGGL((cg_spmv_pq<T, NW>), gs, bs, 0, s, c.n, c.ix, c.val, c.p, c.q, c.part, c.st, c.w)
+    RP_DISPATCH_NW(c.xw_mode, RP_LAUNCH);
+#undef RP_LAUNCH
+    RP_TRY(timing_end(c.plan, c.kernel_id, s));
+    hipLaunchKernelGGL(cg_update_r<T>, gv, bv, 0, s, c.n, k, c.g_spmv, c.r, c.q, c.dinv, c.part, c.st);
+    hipLaunchKernelGGL(cg_update_xp<T>, gv, bv, 0, s, c.n, k, c.g_vec, 0, c.r, c.dinv, c.x, c.p, c.part, c.st);
+    RP_HIP_TRY(hipGetLastError());
+    return RP_OK;
+}
+
+// The executable graph of `chunk` iterations for this Cg, captured on the
+// plan's own stream and instantiated once; captured again when any kernel
+// argument differs from the cached one's.
+template <typename T>
+int cg_graph(Cg<T>& c, int chunk, hipGraphExec_t* out) {
+    rp_plan* p = c.plan;
+    auto& g = p->cg_graph[sizeof(T) == 4 ? 1 : 0];
+    const uint64_t key[24] = {(uint64_t)c.n,           (uint64_t)chunk,        (uint64_t)(uintptr_t)c.val,
+                              (uint64_t)(uintptr_t)c.dinv, (uint64_t)(uintptr_t)c.x, (uint64_t)(uintptr_t)c.r,
+                              (uint64_t)(uintptr_t)c.p,    (uint64_t)(uintptr_t)c.q, (uint64_t)(uintptr_t)c.part,
+                              (uint64_t)(uintptr_t)c.st,   (uint64_t)(uintptr_t)c.ix.row_ptr,
+                              (uint64_t)(uintptr_t)c.ix.col, (uint64_t)(uintptr_t)c.ix.goi_k,
+                              (uint64_t)(uintptr_t)c.ix.goi_off, (uint64_t)(uintptr_t)c.ix.goi_mask,
+                              (uint64_t)c.g_spmv,       (uint64_t)c.g_vec,      (uint64_t)(uint32_t)c.xw_mode,
+                              (uint64_t)(uint32_t)c.w.d[0], (uint64_t)(uint32_t)c.w.d[1], 1, 0, 0, 0};
+    if (g.exec && std::memcmp(g.key, key, sizeof key) == 0) {
+        *out = g.exec;
+        return RP_OK;
+    }
+    if (g.exec) {
+        RP_HIP_TRY(hipGraphExecDestroy(g.exec));
+        g.exec = nullptr;
+    }
+    if (!p->capture_stream) RP_HIP_TRY(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = p->capture_stream;
+    RP_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int rc = RP_OK;
+    for (int i = 0; i < chunk && rc == RP_OK; ++i) rc = launch_iteration(c, -1, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (rc != RP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    RP_HIP_TRY(e);
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    RP_HIP_TRY(ei);
+    std::memcpy(g.key, key, sizeof key);
+    *out = g.exec;
+    return RP_OK;
+}
+
+// enqueue chunks of up to `chunk` iterations (never past max_iter) until the
+// state leaves CG_RUNNING or the budget is spent.  graph: each chunk is one
+// replay of a captured graph of `chunk` iterations (kernels past max_iter do
+// nothing); per-kernel timing always launches eagerly.
+template <typename T>
+int iterate(Cg<T>& c, int chunk, int32_t max_iter, bool graph) {
+    const bool timed = c.plan->timing.enabled;
+    hipGraphExec_t exec = nullptr;
+    if (graph && !timed) RP_TRY(cg_graph(c, chunk, &exec));
     while (c.h->done == CG_RUNNING && c.h->iter < max_iter) {
         const int32_t k0 = c.h->iter;
-        const int32_t k1 = (int32_t)std::min<int64_t>((int64_t)k0 + chunk, max_iter);
-        for (int32_t k = k0; k < k1; ++k) {
-            RP_TRY(timing_begin(c.plan, c.kernel_id, c.s));
-#define RP_LAUNCH(NW)                                                                                          \
-    hipLaunchKernelGGL((cg_spmv_pq<T, NW>), gs, bs, 0, c.s, c.n, c.ix, c.val, c.p, c.q, c.part, c.st, \
-                       c.w)
-            RP_DISPATCH_NW(c.xw_mode, RP_LAUNCH);
-#undef RP_LAUNCH
-            RP_TRY(timing_end(c.plan, c.kernel_id, c.s));
-            hipLaunchKernelGGL(cg_update_r<T>, gv, bv, 0, c.s, c.n, k, c.g_spmv, c.r, c.q, c.dinv, c.part, c.st);
-            hipLaunchKernelGGL(cg_update_xp<T>, gv, bv, 0, c.s, c.n, k, c.g_vec, 0, c.r, c.dinv, c.x, c.p, c.part,
-                               c.st);
+        if (exec) {
+            RP_HIP_TRY(hipGraphLaunch(exec, c.s));
+        } else {
+            const int32_t k1 = (int32_t)std::min<int64_t>((int64_t)k0 + chunk, max_iter);
+            for (int32_t k = k0; k < k1; ++k) RP_TRY(launch_iteration(c, k, c.s));
         }
-        RP_HIP_TRY(hipGetLastError());
         RP_TRY(read_state(c));
-        RP_TRY(timing_collect(c.plan, c.kernel_id, (int64_t)c.h->iter - k0));
+        if (!exec) RP_TRY(timing_collect(c.plan, c.kernel_id, (int64_t)c.h->iter - k0));
     }
     return RP_OK;
 }
@@ -426,7 +494,7 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
     const double tol2 = o.tol * o.tol;
     const int chunk = std::max(1, o.check_every);
     RP_TRY((launch_residual<double, false>(c, o.x0_zero != 0, nullptr)));
-    RP_TRY(launch_start(c, 0, tol2, 0.0));
+    RP_TRY(launch_start(c, 0, tol2, 0.0, o.max_iter));
     RP_TRY(read_state(c));
     bool fresh = true;  // rr_true belongs to the current x
     int status = RP_NOT_CONVERGED;
@@ -452,7 +520,7 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
             }
             if (info.restarts >= o.max_restarts) break;
             ++info.restarts;
-            RP_TRY(launch_start(c, c.h->iter, tol2, 0.0));
+            RP_TRY(launch_start(c, c.h->iter, tol2, 0.0, o.max_iter));
             RP_TRY(read_state(c));
             continue;
         }
@@ -462,7 +530,7 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
             break;
         }
         if (c.h->iter >= o.max_iter) break;
-        RP_TRY(iterate(c, chunk, o.max_iter));
+        RP_TRY(iterate(c, chunk, o.max_iter, o.graph != 0));
         fresh = false;
     }
     if (!fresh && c.h->done != CG_ZERO_RHS) {
@@ -516,12 +584,12 @@ int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, 
     while (status != RP_OK) {
         if (start_inner) {
             RP_TRY((launch_residual<float, false>(in, true, nullptr)));
-            RP_TRY(launch_start(in, total_inner, tol2_in, pause2));
+            RP_TRY(launch_start(in, total_inner, tol2_in, pause2, o.max_iter));
             RP_TRY(read_state(in));
             start_inner = false;
         }
         const int32_t it_before = in.h->iter;
-        RP_TRY(iterate(in, chunk, o.max_iter));
+        RP_TRY(iterate(in, chunk, o.max_iter, o.graph != 0));
         total_inner = in.h->iter;
         const int32_t d = in.h->done;
         // fold the FP32 correction into x and take the FP64 residual

@@ -76,6 +76,8 @@ struct CgState {
     S pause_thresh; // pause_frac2 * rr_ref
     int32_t iter;   // completed iterations
     int32_t done;   // CG_*
+    int32_t max_iter;  // iteration budget (kernels past it do nothing)
+    int32_t kk;        // iteration K2 works on, for K3 (-1: budget spent)
 };
 
 // Device-side scalars of one BiCGStab solve (FP64)
@@ -189,6 +191,13 @@ struct rp_plan {
     int32_t xw_d[2] = {0, 0};
 
     hipStream_t last_stream = nullptr;
+
+    // captured CG iteration chunks (rp_solve_opts.graph), [0] FP64, [1] FP32
+    hipStream_t capture_stream = nullptr;
+    struct CgGraph {
+        hipGraphExec_t exec = nullptr;
+        uint64_t key[24] = {};
+    } cg_graph[2];
     rp::Timing timing;
 };
 

@@ -68,7 +68,7 @@ int main(void) {
   F(rp_solve_opts, tol); F(rp_solve_opts, inner_tol); F(rp_solve_opts, update_delta); F(rp_solve_opts, max_iter);
   F(rp_solve_opts, precision);
   F(rp_solve_opts, max_outer); F(rp_solve_opts, check_every); F(rp_solve_opts, x0_zero);
-  F(rp_solve_opts, max_restarts); F(rp_solve_opts, method); F(rp_solve_opts, transpose);
+  F(rp_solve_opts, max_restarts); F(rp_solve_opts, method); F(rp_solve_opts, transpose); F(rp_solve_opts, graph);
   F(rp_solve_info, status); F(rp_solve_info, iters); F(rp_solve_info, outer_iters); F(rp_solve_info, restarts);
   F(rp_solve_info, rel_res);
   F(rp_spmv_format, enabled); F(rp_spmv_format, reserved); F(rp_spmv_format, n_groups);
@@ -95,7 +95,7 @@ def test_opts_defaults(lib_path):
     import paper_2510_08536_amd.rp as rp
     o = rp.default_opts()
     assert o.tol == 1e-8 and o.inner_tol == 1e-4 and o.precision == rp.RP_FP64 and o.check_every > 0
-    assert o.update_delta == 0.1 and o.max_outer > 0 and o.method == rp.RP_CG and o.transpose == 0
+    assert o.update_delta == 0.1 and o.max_outer > 0 and o.method == rp.RP_CG and o.transpose == 0 and o.graph == 0
 
 
 def test_missing_library_fails_loudly():
