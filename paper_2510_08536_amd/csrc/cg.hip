@@ -162,7 +162,7 @@ cg_spmv_pq(int32_t n, SpmvIdx ix, const T* __restrict__ val, const T* __restrict
         if ((int32_t)threadIdx.x < nr) {
             const int32_t i = r0 + threadIdx.x;
             q[i] = gr_.s;
-            ppq += own_x<T, NW>(i, gr_.coded, xs, p) * gr_.s;
+            ppq += own_x<T, NW>(i, gr_, xs, p) * gr_.s;
         }
     }
     const T b = block_sum<T, SPMV_BLOCK>(ppq, red);

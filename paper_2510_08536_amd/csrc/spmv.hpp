@@ -76,6 +76,7 @@ template <typename T>
 struct GroupRow {
     T s;         // row sum of the thread's row
     bool coded;  // the group ran offset-coded (no x windows staged)
+    T xi;        // coded: x of the thread's row
 };
 
 // cache-policy bits of the direct-to-LDS loads: non-temporal (streamed once)
@@ -228,9 +229,9 @@ __device__ __forceinline__ T spmv_group_csr(const int32_t* __restrict__ row_ptr,
 // aligned 16-byte packs (2 doubles or 4 floats); when the plan is built, a
 // group is coded only if its packs fit SPMV_CAP elements in both precisions.
 template <typename T>
-__device__ __forceinline__ T spmv_group_coded(const SpmvIdx& ix, const T* __restrict__ val,
-                                             const T* __restrict__ x, int32_t g, int32_t K, int32_t r0,
-                                             int32_t nr, T* lds) {
+__device__ __forceinline__ GroupRow<T> spmv_group_coded(const SpmvIdx& ix, const T* __restrict__ val,
+                                                      const T* __restrict__ x, int32_t n, int32_t g,
+                                                      int32_t K, int32_t r0, int32_t nr, T* lds) {
 #pragma clang fp contract(off)
     typedef typename Pack<T>::type VP;
     constexpr int E = Pack<T>::E;
@@ -245,6 +246,18 @@ __device__ __forceinline__ T spmv_group_coded(const SpmvIdx& ix, const T* __rest
     const int32_t npk = (end - al + E - 1) / E;
     const int32_t last = npk > 0 ? npk - 1 : 0;
     const uint32_t m = t < nr ? (uint32_t)ix.goi_mask[r0 + t] : 0u;
+    // FP64: the block's diagonal window x[r0 - XN, r0 + SPMV_BLOCK + XN) goes
+    // to LDS, and taps with |offset| <= XN read it there instead of memory.
+    // (FP32 runs slower with it and takes every tap from memory.)
+    constexpr bool XWIN = sizeof(T) == 8;
+    constexpr int XN = 64;
+    __shared__ T xd[XWIN ? SPMV_BLOCK + 2 * XN : 1];
+    T xa = T(0), xb = T(0);
+    if constexpr (XWIN) {
+        const int32_t e0 = r0 - XN + t, e1 = e0 + SPMV_BLOCK;
+        if (e0 >= 0 && e0 < n) xa = x[e0];
+        if (t < 2 * XN && e1 < n) xb = x[e1];
+    }
     __syncthreads();  // the previous group's LDS reads are done before any load lands there
     // the row's first entry: exclusive prefix of the row lengths (popcounts)
     const int32_t c = __popc(m);
@@ -263,24 +276,59 @@ __device__ __forceinline__ T spmv_group_coded(const SpmvIdx& ix, const T* __rest
         __builtin_amdgcn_global_load_lds((void*)(reinterpret_cast<const VP*>(val + al) + min(t + u * SPMV_BLOCK, last)),
                                          (LdsPtr)(reinterpret_cast<VP*>(lds) + u * SPMV_BLOCK + wave0), 16, 0,
                                          SPMV_NT_AUX);
-    // x of every present entry, all issued before the first use
-    T gx[GOI_KMAX];
+    // x of the present entries of the first KH taps, all issued before the
+    // first use; taps KH.. (groups with more offsets) follow after the sums.
+    // FP64 takes 8 at a time: the registers of all 16 would cost it a wave
+    // per SIMD.  FP32 fits all 16 at full occupancy.
+    constexpr int KH = XWIN ? GOI_KMAX / 2 : GOI_KMAX;
+    T gx[KH];
+    if constexpr (XWIN) {
 #pragma unroll
-    for (int j = 0; j < GOI_KMAX; ++j) gx[j] = (j < K && ((m >> j) & 1u)) ? x[r0 + t + off[j]] : T(0);
+        for (int j = 0; j < KH; ++j)
+            gx[j] = (j < K && (off[j] < -XN || off[j] > XN) && ((m >> j) & 1u)) ? x[r0 + t + off[j]] : T(0);
+        xd[t] = xa;
+        if (t < 2 * XN) xd[t + SPMV_BLOCK] = xb;
+    } else {
+#pragma unroll
+        for (int j = 0; j < KH; ++j) gx[j] = (j < K && ((m >> j) & 1u)) ? x[r0 + t + off[j]] : T(0);
+    }
     // the packs of every wave must be in LDS before any wave reads them: wait
     // for all of this wave's loads, then the barrier
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    if constexpr (XWIN) {
+#pragma unroll
+        for (int j = 0; j < KH; ++j)
+            if (j < K && off[j] >= -XN && off[j] <= XN && ((m >> j) & 1u)) gx[j] = xd[XN + t + off[j]];
+    }
     int32_t pos = inc - c + (base - al);
     for (int q = 0; q < (t >> 6); ++q) pos += wtot[q];
     T s = T(0);
 #pragma unroll
-    for (int j = 0; j < GOI_KMAX; ++j)
+    for (int j = 0; j < KH; ++j)
         if (j < K && ((m >> j) & 1u)) {
             s += lds[pos] * gx[j];
             ++pos;
         }
-    return s;
+    if (KH < GOI_KMAX && K > KH) {
+#pragma unroll
+        for (int j = KH; j < GOI_KMAX; ++j) {
+            T v = T(0);
+            if (j < K && ((m >> j) & 1u)) {
+                if (XWIN && off[j] >= -XN && off[j] <= XN) v = xd[XN + t + off[j]];
+                else v = x[r0 + t + off[j]];
+            }
+            gx[j - KH] = v;
+        }
+#pragma unroll
+        for (int j = KH; j < GOI_KMAX; ++j)
+            if (j < K && ((m >> j) & 1u)) {
+                s += lds[pos] * gx[j - KH];
+                ++pos;
+            }
+    }
+    if constexpr (XWIN) return GroupRow<T>{s, true, xd[XN + t]};
+    return GroupRow<T>{s, true, t < nr ? x[r0 + t] : T(0)};
 }
 
 // Row sum of row g * SPMV_BLOCK + threadIdx.x in the form chosen for group g.
@@ -291,16 +339,17 @@ __device__ __forceinline__ GroupRow<T> spmv_group_row(const SpmvIdx& ix, const T
     const int32_t r0 = g * SPMV_BLOCK;
     if (ix.goi_k != nullptr) {
         const int32_t K = ix.goi_k[g];
-        if (K > 0) return GroupRow<T>{spmv_group_coded<T>(ix, val, x, g, K, r0, nr, lds), true};
+        if (K > 0) return spmv_group_coded<T>(ix, val, x, n, g, K, r0, nr, lds);
     }
-    return GroupRow<T>{spmv_group_csr<T, NW>(ix.row_ptr, ix.col, val, x, n, r0, nr, w, xs, lds), false};
+    return GroupRow<T>{spmv_group_csr<T, NW>(ix.row_ptr, ix.col, val, x, n, r0, nr, w, xs, lds), false, T(0)};
 }
 
-// x of row i = r0 + threadIdx.x after spmv_group_row (from the diagonal
-// window when the group ran in CSR form with windows)
+// x of row i = r0 + threadIdx.x after spmv_group_row (kept by the coded
+// form; from the diagonal window when the group ran in CSR form with windows)
 template <typename T, int NW>
-__device__ __forceinline__ T own_x(int32_t i, bool coded, const T* xs, const T* __restrict__ x) {
-    if (NW >= 0 && !coded) return xs[XW_HALF + threadIdx.x];
+__device__ __forceinline__ T own_x(int32_t i, const GroupRow<T>& gr, const T* xs, const T* __restrict__ x) {
+    if (gr.coded) return gr.xi;
+    if (NW >= 0) return xs[XW_HALF + threadIdx.x];
     return x[i];
 }
 
