@@ -196,7 +196,29 @@ cg_update_r(int32_t n, int32_t k_arg, int32_t g_spmv, T* __restrict__ r, const T
     }
     const T a = st->rz[k & 3] / pq;
     T prz = T(0), prr = T(0);
-    for (int32_t i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK) {
+    const int32_t di = gridDim.x * VEC_BLOCK;
+    int32_t i = blockIdx.x * VEC_BLOCK + threadIdx.x;
+    // U of the thread's grid-stride elements per trip, all loads first; the
+    // sums take the elements in the plain loop's order
+    constexpr int U = vec_unroll<T>();
+    for (; (int64_t)i + (int64_t)(U - 1) * di < n; i += U * di) {
+        T rv[U], qv[U], dv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            rv[u] = r[i + u * di];
+            qv[u] = q[i + u * di];
+            dv[u] = dinv[i + u * di];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const T ri = rv[u] - a * qv[u];
+            r[i + u * di] = ri;
+            const T zi = dv[u] * ri;
+            prz += ri * zi;
+            prr += ri * ri;
+        }
+    }
+    for (; i < n; i += di) {
         const T ri = r[i] - a * q[i];
         r[i] = ri;
         const T zi = dinv[i] * ri;
@@ -255,7 +277,24 @@ cg_update_xp(int32_t n, int32_t k_arg, int32_t g_vec, int32_t resume, const T* _
     if (resume) {
         for (int32_t i = i0; i < n; i += di) p[i] = dinv[i] * r[i] + beta * p[i];
     } else {
-        for (int32_t i = i0; i < n; i += di) {
+        int32_t i = i0;
+        constexpr int U = vec_unroll<T>();
+        for (; (int64_t)i + (int64_t)(U - 1) * di < n; i += U * di) {
+            T rv[U], dv[U], xv[U], pv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                rv[u] = r[i + u * di];
+                dv[u] = dinv[i + u * di];
+                xv[u] = x[i + u * di];
+                pv[u] = p[i + u * di];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                x[i + u * di] = xv[u] + a * pv[u];
+                p[i + u * di] = dv[u] * rv[u] + beta * pv[u];
+            }
+        }
+        for (; i < n; i += di) {
             const T pi = p[i];
             x[i] = x[i] + a * pi;
             p[i] = dinv[i] * r[i] + beta * pi;
