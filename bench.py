@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12,
                     help="oracle PCG iterations timed for the CPU baseline sample")
+    ap.add_argument("--solve-order", default="fused", choices=["fused", "rcm"],
+                    help="row order CG and the mixed solvers run in (rcm: the plan's reverse Cuthill-McKee copy)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 2 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -111,6 +113,13 @@ def main():
     plan_ms = 1e3 * (time.perf_counter() - t0)
     n, nnz = plan.n_rows, plan.nnz
     print(f"[bench] plan: n={n} nnz={nnz} slots={plan.n_slots} in {plan_ms:.1f} ms", flush=True)
+    order_ms = None
+    if a.solve_order == "rcm":
+        t0 = time.perf_counter()
+        plan.set_solve_order("rcm")
+        torch.cuda.synchronize()
+        order_ms = 1e3 * (time.perf_counter() - t0)
+        print(f"[bench] solve order (reverse Cuthill-McKee) built in {order_ms:.1f} ms", flush=True)
 
     # ---- per-timestep inputs, resident in HBM before timing ------------------
     def to_dev(v):
@@ -260,8 +269,11 @@ def main():
     iter32_bytes = 8 * nnz + 56 * n
     # BiCGStab iteration: two CSR SpMVs plus 168 n of vectors (p, y, v, rh, s, z, t, x, r)
     iterbi_bytes = 2 * (12 * nnz + 20 * n) + 168 * n
-    kern64_bytes = fmt["bytes64"]            # what the SpMV kernels read and write in the form in use
-    kern32_bytes = fmt["bytes32"]
+    kern64_fused = fmt["bytes64"]            # what the SpMV kernels read and write in the form in use
+    # the solves' SpMV: the fused form, or plain CSR groups on the solve-order copy
+    rcm = a.solve_order == "rcm"
+    kern64_bytes = spmv64_bytes if rcm else fmt["bytes64"]
+    kern32_bytes = spmv32_bytes if rcm else fmt["bytes32"]
     spmv_avg_ms = ms_spmv / max(n_spmv, 1)
     spmv32_avg_ms = ms_spmv32 / max(n_spmv32, 1)
     spmv_gbs = spmv64_bytes / (spmv_avg_ms * 1e-3) / 1e9
@@ -282,7 +294,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{a.config}: {w.recipe.note}", "n_rows": n, "nnz": nnz, "alpha": w.n_ranks,
-                   "tol": 1e-8, "x0": "zero",
+                   "tol": 1e-8, "x0": "zero", "solve_order": a.solve_order,
                    "step": "update + FP64 PCG + mixed PCG + adjoint (lambda solve + slot gradient) + "
                            "momentum update + BiCGStab"},
         "fp64": {"ms_per_solve": round(med(f64), 3), "iters": int(np.median(it64)),
@@ -307,22 +319,25 @@ def main():
         "update_scatter_ms": round(ms_scat / max(n_scat, 1), 4),
         "update_host_staged_ms": round(update_host_ms, 3),
         "plan_ms": round(plan_ms, 1),
+        "solve_order_build_ms": None if order_ms is None else round(order_ms, 1),
         "spmv_GBps": round(spmv_gbs, 1),
         "spmv32_GBps": round(spmv32_gbs, 1),
         "spmv_alone": {"median_us": round(spmv_micro_us, 2), "launches": 200,
                        "GBps": round(spmv64_bytes / (spmv_micro_us * 1e-6) / 1e9, 1),
-                       "kernel_GBps": round(kern64_bytes / (spmv_micro_us * 1e-6) / 1e9, 1)},
+                       "kernel_GBps": round(kern64_fused / (spmv_micro_us * 1e-6) / 1e9, 1)},
         "spmv_format": {"coded_groups": fmt["coded_groups"], "n_groups": fmt["n_groups"],
                         "coded_nnz_frac": round(fmt["coded_nnz"] / max(nnz, 1), 4),
                         "kernel_bytes64": kern64_bytes, "kernel_GBps64": round(kern64_bytes / (spmv_avg_ms * 1e-3) / 1e9, 1),
                         "kernel_bytes32": kern32_bytes,
                         "kernel_GBps32": round(kern32_bytes / (spmv32_avg_ms * 1e-3) / 1e9, 1)},
-        "roofline": {"bound": "hbm", "kernel": "cg_spmv_pq<double> (FP64 SpMV + p.q; offset-coded row groups)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "cg_spmv_pq<double> (FP64 SpMV + p.q; " + (
+                         "CSR groups on the reverse Cuthill-McKee solve order)" if rcm else "offset-coded row groups)"),
                      "achieved": round(spmv_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(spmv_gbs / HBM_PEAK_GBS, 4),
                      "bytes_per_launch": spmv64_bytes, "bytes_basis": "12 nnz + 20 n + 4 (FP64 CSR SpMV)",
                      "kernel_bytes_per_launch": kern64_bytes, "avg_launch_ms": round(spmv_avg_ms, 5),
-                     "launches": n_spmv, "traffic": profiled_traffic(a.config),
+                     "launches": n_spmv, "traffic": None if rcm else profiled_traffic(a.config),
                      "traffic_note": "HBM bytes/launch from FETCH_SIZE+WRITE_SIZE (profiles/traffic_c3.md), "
                                      "scaled by a 2 GiB copy; null if the kernel changed since"},
     }

@@ -191,6 +191,34 @@ int rp_plan_spmv_format(const rp_plan* plan, rp_spmv_format* info);
 /* enable = 0: every group as CSR; 1: coded groups where built (default). */
 int rp_plan_set_spmv_format(rp_plan* plan, int32_t enable);
 
+/* ---- solve order (an implementation choice; the paper's CG of Sec. 4 is
+ * unchanged, only the numbering it runs in) ------------------------------- *
+ * mode 0 (default): CG and the mixed solvers run on the fused row order.
+ * mode 1: they run on a reverse Cuthill-McKee renumbering of the fused local
+ * block.  The first call with mode 1 builds it (pattern downloaded, order and
+ * renumbered CSR computed on the host, uploaded; synchronises the device).
+ * The renumbered values follow every update through one gather, done by the
+ * next solve.  b and x of rp_solve stay in fused order; the solve permutes
+ * them in and out.  The pattern, P, rp_update_values*, rp_spmv,
+ * rp_value_grad and BiCGStab keep the fused order.  Results equal the fused
+ * order's up to rounding (each row's products are summed in ascending
+ * renumbered column).  Pays off where the fused numbering has no locality
+ * (scrambled meshes); on a naturally ordered mesh it replaces the
+ * offset-coded SpMV by plain CSR and is slower.  mode 0 or 1, else
+ * RP_ERR_ARG; a share with non-local entries: RP_ERR_UNSUPPORTED. */
+int rp_plan_set_solve_order(rp_plan* plan, int32_t mode);
+/* *mode (nullable): the current mode.  perm[n_rows] (nullable): the fused
+ * row at each solve-order position; RP_ERR_ARG if no order was built. */
+int rp_plan_solve_order(const rp_plan* plan, int32_t* mode, int32_t* perm);
+/* The ordering itself, on host arrays (no device work): reverse
+ * Cuthill-McKee of the n x n pattern (row_ptr[n+1] from 0, col[row_ptr[n]]
+ * in [0, n), structurally symmetric; diagonal entries ignored).  Each
+ * connected component, in order of its lowest row, starts from a
+ * pseudo-peripheral row; neighbours are visited by ascending degree, ties by
+ * index; the order is then reversed.  perm[k] = the row placed at k.
+ * RP_ERR_ARG on a malformed pattern. */
+int rp_rcm_order(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* perm);
+
 /* ---- update (Sec. 3, update procedure) --------------------------------- *
  * diag/upper/lower/iface: arrays of alpha pointers (host array), pointer s
  * giving rank first_rank+s's values in its LDU order (host or device memory).

@@ -76,7 +76,8 @@ void free_plan(rp_plan* p) {
                    p->d_val64, p->d_val32, p->d_dinv64, p->d_dinv32, p->d_r, p->d_p, p->d_q, p->d_r32,
                    p->d_p32, p->d_q32, p->d_x32, p->d_partials, p->d_st64, p->d_st32, p->d_st_outer,
                    p->d_flags, p->d_goi_k, p->d_goi_off, p->d_goi_mask, p->d_bi_st, p->d_bi_work,
-                   p->d_valT, p->d_tflag};
+                   p->d_valT, p->d_tflag, p->d_ro_perm, p->d_ro_row_ptr, p->d_ro_col, p->d_ro_sig,
+                   p->d_ro_val64, p->d_ro_val32, p->d_ro_dinv64, p->d_ro_dinv32, p->d_ro_b, p->d_ro_x};
     for (void* q : dev)
         if (q) (void)hipFree(q);
     if (p->h_st64) (void)hipHostFree(p->h_st64);
@@ -453,6 +454,8 @@ int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, 
         rc = RP_OK;
     } else if (o.method == RP_BICGSTAB) {
         rc = solve_bicgstab(p, b, x, o, inf, s);
+    } else if (p->ro_mode == 1) {
+        rc = solve_in_order(p, b, x, o, inf, s);
     } else if (o.precision == RP_FP64) {
         rc = solve_fp64(p, b, x, o, inf, s);
     } else {
@@ -460,6 +463,46 @@ int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, 
     }
     inf.status = rc;
     return rc;
+}
+
+int rp_plan_set_solve_order(rp_plan* p, int32_t mode) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    RP_CHECK(mode == 0 || mode == 1, RP_ERR_ARG, "solve order must be 0 (fused) or 1 (reverse Cuthill-McKee)");
+    RP_CHECK(mode == 0 || p->nnz_nl == 0, RP_ERR_UNSUPPORTED,
+             "the solve order needs a share without non-local entries");
+    RP_TRY(activate(p));
+    if (mode == 1 && p->d_ro_perm == nullptr && p->n_rows > 0) {
+        RP_HIP_TRY(hipDeviceSynchronize());
+        RP_TRY(order_build(p));
+    }
+    p->ro_mode = mode;
+    return RP_OK;
+}
+
+int rp_plan_solve_order(const rp_plan* p, int32_t* mode, int32_t* perm) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    if (mode) *mode = p->ro_mode;
+    if (perm) {
+        RP_CHECK(p->ro_mode == 1 || !p->h_ro_perm.empty(), RP_ERR_ARG,
+                 "no solve order built (rp_plan_set_solve_order(plan, 1) first)");
+        std::copy(p->h_ro_perm.begin(), p->h_ro_perm.end(), perm);
+    }
+    return RP_OK;
+}
+
+int rp_rcm_order(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* perm) {
+    clear_error();
+    RP_CHECK(n >= 0 && (n == 0 || (row_ptr && perm)), RP_ERR_ARG, "bad arguments");
+    RP_CHECK(row_ptr == nullptr || row_ptr[0] == 0, RP_ERR_ARG, "row_ptr[0] must be 0");
+    for (int32_t i = 0; i < n; ++i) RP_CHECK(row_ptr[i + 1] >= row_ptr[i], RP_ERR_ARG, "row_ptr decreases");
+    const int64_t nnz = n > 0 ? row_ptr[n] : 0;
+    RP_CHECK(nnz == 0 || col != nullptr, RP_ERR_ARG, "col is NULL");
+    for (int64_t j = 0; j < nnz; ++j) RP_CHECK(col[j] >= 0 && col[j] < n, RP_ERR_ARG, "column out of range");
+    const std::vector<int32_t> o = rcm_order(n, row_ptr, col);
+    std::copy(o.begin(), o.end(), perm);
+    return RP_OK;
 }
 
 int rp_value_grad(rp_plan* p, const double* lambda, const double* x, double* g_slots, void* stream) {

@@ -352,11 +352,23 @@ struct Cg {
     XWin w;
 };
 
+// the matrix a solve runs on: the fused pattern in the plan's SpMV form, or
+// the solve-order copy (plain CSR groups, no x windows)
+struct MatView {
+    SpmvIdx ix;
+    int32_t xw_mode;
+};
+
+MatView mat_view(rp_plan* p, bool ordered) {
+    if (ordered) return MatView{SpmvIdx{p->d_ro_row_ptr, p->d_ro_col, nullptr, nullptr, nullptr}, -1};
+    return MatView{spmv_idx(p), p->xw_mode};
+}
+
 template <typename T>
-Cg<T> make_cg(rp_plan* p, const T* val, const T* dinv, T* x, const T* b, T* r, T* pv, T* q, CgState<T>* st,
-              CgState<T>* h, int kernel_id, hipStream_t s) {
-    Cg<T> c{p, (int32_t)p->n_rows, spmv_idx(p), val, dinv, x, b, r, pv, q, (T*)p->d_partials, st, h,
-            kernel_id, s, spmv_grid(p->n_rows), vec_grid(p->n_rows), p->xw_mode, XWin{{p->xw_d[0], p->xw_d[1]}}};
+Cg<T> make_cg(rp_plan* p, const MatView& m, const T* val, const T* dinv, T* x, const T* b, T* r, T* pv, T* q,
+              CgState<T>* st, CgState<T>* h, int kernel_id, hipStream_t s) {
+    Cg<T> c{p, (int32_t)p->n_rows, m.ix, val, dinv, x, b, r, pv, q, (T*)p->d_partials, st, h,
+            kernel_id, s, spmv_grid(p->n_rows), vec_grid(p->n_rows), m.xw_mode, XWin{{p->xw_d[0], p->xw_d[1]}}};
     return c;
 }
 
@@ -526,10 +538,12 @@ int check_solvable(rp_plan* p, hipStream_t s, bool need_symmetric = true) {
 }  // namespace
 
 int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
-               hipStream_t s) {
+               hipStream_t s, bool ordered) {
     RP_TRY(check_solvable(p, s));
-    Cg<double> c = make_cg<double>(p, p->d_val64, p->d_dinv64, x, b, p->d_r, p->d_p, p->d_q, p->d_st64,
-                                   p->h_st64, RP_KERNEL_SPMV64, s);
+    const MatView m = mat_view(p, ordered);
+    Cg<double> c = make_cg<double>(p, m, ordered ? p->d_ro_val64 : p->d_val64,
+                                   ordered ? p->d_ro_dinv64 : p->d_dinv64, x, b, p->d_r, p->d_p, p->d_q,
+                                   p->d_st64, p->h_st64, RP_KERNEL_SPMV64, s);
     const double tol2 = o.tol * o.tol;
     const int chunk = std::max(1, o.check_every);
     RP_TRY((launch_residual<double, false>(c, o.x0_zero != 0, nullptr)));
@@ -587,14 +601,17 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
 }
 
 int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
-                hipStream_t s, bool reliable) {
+                hipStream_t s, bool reliable, bool ordered) {
     RP_TRY(check_solvable(p, s));
+    const MatView m = mat_view(p, ordered);
     // FP64: r64 = b - A x and its norm; x is the FP64 solution
-    Cg<double> out = make_cg<double>(p, p->d_val64, p->d_dinv64, x, b, p->d_r, p->d_p, p->d_q, p->d_st_outer,
-                                     p->h_st_outer, RP_KERNEL_SPMV64, s);
+    Cg<double> out = make_cg<double>(p, m, ordered ? p->d_ro_val64 : p->d_val64,
+                                     ordered ? p->d_ro_dinv64 : p->d_dinv64, x, b, p->d_r, p->d_p, p->d_q,
+                                     p->d_st_outer, p->h_st_outer, RP_KERNEL_SPMV64, s);
     // FP32 PCG on A32 d = r32 (b and r alias r32); d is folded into x
-    Cg<float> in = make_cg<float>(p, p->d_val32, p->d_dinv32, p->d_x32, p->d_r32, p->d_r32, p->d_p32, p->d_q32,
-                                  p->d_st32, p->h_st32, RP_KERNEL_SPMV32, s);
+    Cg<float> in = make_cg<float>(p, m, ordered ? p->d_ro_val32 : p->d_val32,
+                                  ordered ? p->d_ro_dinv32 : p->d_dinv32, p->d_x32, p->d_r32, p->d_r32, p->d_p32,
+                                  p->d_q32, p->d_st32, p->h_st32, RP_KERNEL_SPMV32, s);
     const int chunk = std::max(1, o.check_every);
 
     RP_TRY((launch_residual<double, true>(out, o.x0_zero != 0, p->d_r32)));
@@ -991,8 +1008,8 @@ int solve_bicgstab(rp_plan* p, const double* b, double* x, const rp_solve_opts& 
     // A^T x = b: same pattern and diagonal, transposed values
     if (o.transpose) RP_TRY(build_transpose(p, s));
     const double* val = o.transpose ? p->d_valT : p->d_val64;
-    Bi q{make_cg<double>(p, val, p->d_dinv64, x, b, p->d_r, p->d_p, p->d_q, p->d_st64, p->h_st64,
-                         RP_KERNEL_SPMV64, s),
+    Bi q{make_cg<double>(p, mat_view(p, false), val, p->d_dinv64, x, b, p->d_r, p->d_p, p->d_q, p->d_st64,
+                         p->h_st64, RP_KERNEL_SPMV64, s),
          p->d_bi_work, p->d_p, p->d_q, p->d_bi_work + n, p->d_bi_work + 2 * n, p->d_bi_work + 3 * n,
          p->d_bi_work + 4 * n, p->d_bi_st, p->h_bi_st};
     const double tol2 = o.tol * o.tol;

@@ -196,6 +196,21 @@ struct rp_plan {
 
     hipStream_t last_stream = nullptr;
 
+    // solve order (order.hip): 0 fused rows, 1 reverse Cuthill-McKee
+    // renumbering for CG and the mixed solvers (built on first use)
+    int32_t ro_mode = 0;
+    int32_t* d_ro_perm = nullptr;      // [n_rows] fused row of each solve-order row
+    int32_t* d_ro_row_ptr = nullptr;   // [n_rows+1]
+    int32_t* d_ro_col = nullptr;       // [nnz + SPMV_PAD] solve-order columns, ascending per row
+    int32_t* d_ro_sig = nullptr;       // [nnz] fused CSR position of each solve-order position
+    double* d_ro_val64 = nullptr;      // [nnz + SPMV_PAD]
+    float* d_ro_val32 = nullptr;       // [nnz + SPMV_PAD]
+    double* d_ro_dinv64 = nullptr;     // [n_rows]
+    float* d_ro_dinv32 = nullptr;      // [n_rows]
+    double *d_ro_b = nullptr, *d_ro_x = nullptr;  // [n_rows] b and x in solve order
+    std::vector<int32_t> h_ro_perm;
+    int64_t ro_version = -1;           // values_version the solve-order values were gathered from
+
     // captured CG iteration chunks (rp_solve_opts.graph), [0] FP64, [1] FP32
     hipStream_t capture_stream = nullptr;
     struct CgGraph {
@@ -244,15 +259,23 @@ int launch_stage_table(rp_plan* p, bool lower_given, hipStream_t s);
 int launch_spmv64(rp_plan* p, const double* x, double* y, hipStream_t s);
 int launch_spmv32(rp_plan* p, const float* x, float* y, hipStream_t s);
 // cg.hip
+// ordered: run on the solve-order copy (b, x in solve order)
 int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
-               hipStream_t s);
+               hipStream_t s, bool ordered = false);
 // reliable = true: FP32 PCG with FP64 residual replacement (RP_MIXED);
 // false: restarted FP32 inner PCG under FP64 refinement (RP_MIXED_IR)
 int solve_bicgstab(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
                    hipStream_t s);
 int build_transpose(rp_plan* p, hipStream_t s);
 int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
-                hipStream_t s, bool reliable);
+                hipStream_t s, bool reliable, bool ordered = false);
+// order.hip
+// reverse Cuthill-McKee order of a structurally symmetric pattern: perm[k] = row at position k
+std::vector<int32_t> rcm_order(int32_t n, const int32_t* row_ptr, const int32_t* col);
+int order_build(rp_plan* p);
+// CG / mixed solve on the solve-order copy; b and x in fused order
+int solve_in_order(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
+                   hipStream_t s);
 // grad.hip
 int launch_value_grad(rp_plan* p, const double* lambda, const double* x, double* g, hipStream_t s);
 

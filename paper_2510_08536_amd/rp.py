@@ -46,7 +46,8 @@ STATUS_NAMES = {0: "RP_OK", 1: "RP_NOT_CONVERGED", -1: "RP_ERR_ARG", -2: "RP_ERR
 EXPORTED = ["rp_plan_create", "rp_plan_destroy", "rp_plan_sizes", "rp_plan_get_csr", "rp_plan_get_values",
             "rp_plan_spmv_windows", "rp_plan_set_spmv_windows", "rp_plan_spmv_format", "rp_plan_set_spmv_format",
             "rp_update_values", "rp_update_values_slots", "rp_spmv", "rp_solve", "rp_solve_opts_default",
-            "rp_value_grad", "rp_sync", "rp_last_error", "rp_plan_set_timing", "rp_plan_kernel_stats"]
+            "rp_value_grad", "rp_sync", "rp_last_error", "rp_plan_set_timing", "rp_plan_kernel_stats",
+            "rp_plan_set_solve_order", "rp_plan_solve_order", "rp_rcm_order"]
 
 
 class rp_rank_desc(C.Structure):
@@ -107,6 +108,9 @@ _sig = {
     "rp_last_error": (C.c_char_p, []),
     "rp_plan_set_timing": (C.c_int, [_P, C.c_int32]),
     "rp_plan_kernel_stats": (C.c_int, [_P, C.c_int32, _i64p, _dblp]),
+    "rp_plan_set_solve_order": (C.c_int, [_P, C.c_int32]),
+    "rp_plan_solve_order": (C.c_int, [_P, _i32p, _P]),
+    "rp_rcm_order": (C.c_int, [C.c_int32, _P, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -151,6 +155,17 @@ def _ptr(t):
     if isinstance(t, np.ndarray):
         return C.c_void_p(t.ctypes.data)
     return C.c_void_p(t.data_ptr())
+
+
+def rcm_order(row_ptr, col) -> np.ndarray:
+    """Reverse Cuthill-McKee order of a structurally symmetric CSR pattern
+    (host arrays, no device work): perm[k] = the row placed at position k."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    n = row_ptr.size - 1
+    perm = np.zeros(max(n, 1), np.int32)
+    _check(rp_rcm_order(n, _ptr(row_ptr), _ptr(col) if col.size else None, _ptr(perm)), "rp_rcm_order")
+    return perm[:n]
 
 
 def default_opts(**kw) -> rp_solve_opts:
@@ -244,6 +259,22 @@ class Plan:
 
     def set_spmv_format(self, coded: bool):
         _check(rp_plan_set_spmv_format(self._h, int(bool(coded))), "rp_plan_set_spmv_format")
+
+    def set_solve_order(self, mode):
+        """0 / "fused": CG and the mixed solvers run on the fused rows;
+        1 / "rcm": on the plan's reverse Cuthill-McKee renumbering (built on
+        first use).  b and x stay in fused order either way."""
+        if isinstance(mode, str):
+            mode = {"fused": 0, "rcm": 1}[mode]
+        _check(rp_plan_set_solve_order(self._h, int(mode)), "rp_plan_set_solve_order")
+
+    def solve_order(self):
+        """(mode, perm): perm[k] = fused row at solve-order position k (None if no order was built)."""
+        mode = C.c_int32()
+        _check(rp_plan_solve_order(self._h, C.byref(mode), None), "rp_plan_solve_order")
+        perm = np.zeros(max(self.n_rows, 1), np.int32)
+        rc = rp_plan_solve_order(self._h, None, _ptr(perm))
+        return mode.value, (perm[:self.n_rows] if rc == RP_OK else None)
 
     def get_csr(self):
         row_ptr = np.zeros(self.n_rows + 1, np.int32)

@@ -202,3 +202,20 @@ def test_c5_scrambled_mixed_and_adjoint():
         gs = plan.value_grad(lam, x).cpu().numpy()
         assert_bits_equal(gs, oracle.value_grad(m, lam.cpu().numpy(), xh), "slot gradient")
     plan.close()
+
+
+def test_c5_fp64_and_mixed_in_rcm_order():
+    """160^3 scrambled: FP64 and mixed PCG on the reverse Cuthill-McKee solve
+    order reach the 1e-8 true residual of the fused system."""
+    w = synth.build("c5")
+    m = oracle.merge(w.part.n_cells, 0, w.n_ranks, share_ranks(w))
+    plan = make_plan(w)
+    plan.set_solve_order("rcm")
+    vals = share_values(w, 0)
+    want = oracle.update(m, oracle.receive_buffer(vals))
+    update(plan, vals)
+    b = w.rhs()
+    for precision in ("fp64", "mixed"):
+        x, info = plan.solve(dev_tensor(b), tol=1e-8, precision=precision)
+        assert info["status"] == 0 and oracle.true_relres(m, want[0], b, x.cpu().numpy()) <= 1e-8, (precision, info)
+    plan.close()
