@@ -191,16 +191,17 @@ int rp_plan_spmv_format(const rp_plan* plan, rp_spmv_format* info);
 /* enable = 0: every group as CSR; 1: coded groups where built (default). */
 int rp_plan_set_spmv_format(rp_plan* plan, int32_t enable);
 
-/* ---- solve order (an implementation choice; the paper's CG of Sec. 4 is
- * unchanged, only the numbering it runs in) ------------------------------- *
- * mode 0 (default): CG and the mixed solvers run on the fused row order.
- * mode 1: they run on a reverse Cuthill-McKee renumbering of the fused local
- * block.  The first call with mode 1 builds it (pattern downloaded, order and
- * renumbered CSR computed on the host, uploaded; synchronises the device).
- * The renumbered values follow every update through one gather, done by the
- * next solve.  b and x of rp_solve stay in fused order; the solve permutes
- * them in and out.  The pattern, P, rp_update_values*, rp_spmv,
- * rp_value_grad and BiCGStab keep the fused order.  Results equal the fused
+/* ---- solve order (an implementation choice; the solvers of Sec. 4 are
+ * unchanged, only the numbering they run in) ------------------------------ *
+ * mode 0 (default): every rp_solve runs on the fused row order.  mode 1:
+ * CG, the mixed solvers and BiCGStab (also transposed) run on a reverse
+ * Cuthill-McKee renumbering of the fused local block.  The first call with
+ * mode 1 builds it (pattern downloaded, order and renumbered CSR computed on
+ * the host, uploaded; synchronises the device).  The renumbered values
+ * follow every update through one gather, done by the next solve.  b and x
+ * of rp_solve stay in fused order; the solve permutes them in and out.  The
+ * pattern, P, rp_update_values*, rp_spmv and rp_value_grad keep the fused
+ * order.  Results equal the fused
  * order's up to rounding (each row's products are summed in ascending
  * renumbered column).  Pays off where the fused numbering has no locality
  * (scrambled meshes); on a naturally ordered mesh it replaces the

@@ -77,7 +77,8 @@ void free_plan(rp_plan* p) {
                    p->d_p32, p->d_q32, p->d_x32, p->d_partials, p->d_st64, p->d_st32, p->d_st_outer,
                    p->d_flags, p->d_goi_k, p->d_goi_off, p->d_goi_mask, p->d_bi_st, p->d_bi_work,
                    p->d_valT, p->d_tflag, p->d_ro_perm, p->d_ro_row_ptr, p->d_ro_col, p->d_ro_sig,
-                   p->d_ro_val64, p->d_ro_val32, p->d_ro_dinv64, p->d_ro_dinv32, p->d_ro_b, p->d_ro_x};
+                   p->d_ro_val64, p->d_ro_val32, p->d_ro_dinv64, p->d_ro_dinv32, p->d_ro_b, p->d_ro_x,
+                   p->d_ro_valT};
     for (void* q : dev)
         if (q) (void)hipFree(q);
     if (p->h_st64) (void)hipHostFree(p->h_st64);
@@ -452,10 +453,10 @@ int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, 
     int rc;
     if (p->n_rows == 0) {
         rc = RP_OK;
-    } else if (o.method == RP_BICGSTAB) {
-        rc = solve_bicgstab(p, b, x, o, inf, s);
     } else if (p->ro_mode == 1) {
         rc = solve_in_order(p, b, x, o, inf, s);
+    } else if (o.method == RP_BICGSTAB) {
+        rc = solve_bicgstab(p, b, x, o, inf, s);
     } else if (o.precision == RP_FP64) {
         rc = solve_fp64(p, b, x, o, inf, s);
     } else {

@@ -1001,15 +1001,17 @@ int bi_iterate(Bi& q, int chunk, int32_t max_iter) {
 }  // namespace
 
 int solve_bicgstab(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
-                   hipStream_t s) {
+                   hipStream_t s, bool ordered) {
     RP_TRY(check_solvable(p, s, false));
     const int64_t n = p->n_rows;
     if (!p->d_bi_work) RP_HIP_TRY(hipMalloc(&p->d_bi_work, sizeof(double) * 5 * (size_t)n));
-    // A^T x = b: same pattern and diagonal, transposed values
-    if (o.transpose) RP_TRY(build_transpose(p, s));
-    const double* val = o.transpose ? p->d_valT : p->d_val64;
-    Bi q{make_cg<double>(p, mat_view(p, false), val, p->d_dinv64, x, b, p->d_r, p->d_p, p->d_q, p->d_st64,
-                         p->h_st64, RP_KERNEL_SPMV64, s),
+    // A^T x = b: same pattern and diagonal, transposed values (the solve-order
+    // copy of them is gathered by the caller)
+    if (o.transpose && !ordered) RP_TRY(build_transpose(p, s));
+    const double* val = ordered ? (o.transpose ? p->d_ro_valT : p->d_ro_val64)
+                                : (o.transpose ? p->d_valT : p->d_val64);
+    Bi q{make_cg<double>(p, mat_view(p, ordered), val, ordered ? p->d_ro_dinv64 : p->d_dinv64, x, b, p->d_r,
+                         p->d_p, p->d_q, p->d_st64, p->h_st64, RP_KERNEL_SPMV64, s),
          p->d_bi_work, p->d_p, p->d_q, p->d_bi_work + n, p->d_bi_work + 2 * n, p->d_bi_work + 3 * n,
          p->d_bi_work + 4 * n, p->d_bi_st, p->h_bi_st};
     const double tol2 = o.tol * o.tol;

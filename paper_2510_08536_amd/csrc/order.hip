@@ -1,5 +1,6 @@
-// Solve order (opt-in, rp_plan_set_solve_order): CG and the mixed solvers
-// run on a reverse Cuthill-McKee renumbering of the fused local block.
+// Solve order (opt-in, rp_plan_set_solve_order): CG, the mixed solvers and
+// BiCGStab run on a reverse Cuthill-McKee renumbering of the fused local
+// block.
 //
 // The fused row order is the ranks' own cell order (Sec. 3).  Where that
 // order has no locality (a scrambled numbering), the SpMV's x gathers touch
@@ -11,7 +12,8 @@
 // renumbered copy is a second CSR matrix Q A Q^T (row k of it is fused row
 // perm[k], columns renumbered and sorted); its values follow the fused
 // values through one gather, refreshed when a solve finds them older than
-// the last update.  b and x are permuted into and out of the solve.
+// the last update (A^T's values, for the transposed BiCGStab solve, the
+// same way).  b and x are permuted into and out of the solve.
 //
 // The renumbered matrix is the same operator in another basis, so the
 // iteration is the same method; only the summation order of each row's
@@ -45,6 +47,13 @@ order_values(int64_t nnz, int32_t n, const int32_t* __restrict__ sig, const int3
         od64[i] = d64[q];
         od32[i] = d32[q];
     }
+}
+
+// o[k] = v[sig[k]]
+__global__ void __launch_bounds__(VEC_BLOCK)
+order_gather(int64_t nnz, const int32_t* __restrict__ sig, const double* __restrict__ v, double* __restrict__ o) {
+    for (int64_t k = (int64_t)blockIdx.x * VEC_BLOCK + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * VEC_BLOCK)
+        o[k] = v[sig[k]];
 }
 
 // y[k] = x[perm[k]]: fused order -> solve order
@@ -185,10 +194,25 @@ int solve_in_order(rp_plan* p, const double* b, double* x, const rp_solve_opts& 
         RP_HIP_TRY(hipGetLastError());
         p->ro_version = p->values_version;
     }
+    if (o.method == RP_BICGSTAB && o.transpose && p->has_values) {
+        // A^T's values on the fused pattern, then in solve order
+        RP_TRY(build_transpose(p, s));
+        if (!p->d_ro_valT) {
+            RP_HIP_TRY(hipMalloc(&p->d_ro_valT, (p->nnz + SPMV_PAD) * sizeof(double)));
+            RP_HIP_TRY(hipMemsetAsync(p->d_ro_valT, 0, (p->nnz + SPMV_PAD) * sizeof(double), s));
+        }
+        if (p->ro_valT_version != p->values_version) {
+            hipLaunchKernelGGL(order_gather, dim3(vec_grid(p->nnz)), dim3(VEC_BLOCK), 0, s, p->nnz, p->d_ro_sig,
+                               p->d_valT, p->d_ro_valT);
+            RP_HIP_TRY(hipGetLastError());
+            p->ro_valT_version = p->values_version;
+        }
+    }
     hipLaunchKernelGGL(order_in, dim3(g), dim3(VEC_BLOCK), 0, s, n, p->d_ro_perm, b, p->d_ro_b);
     if (!o.x0_zero) hipLaunchKernelGGL(order_in, dim3(g), dim3(VEC_BLOCK), 0, s, n, p->d_ro_perm, x, p->d_ro_x);
     RP_HIP_TRY(hipGetLastError());
-    const int rc = o.precision == RP_FP64
+    const int rc = o.method == RP_BICGSTAB ? solve_bicgstab(p, p->d_ro_b, p->d_ro_x, o, info, s, true)
+                   : o.precision == RP_FP64
                        ? solve_fp64(p, p->d_ro_b, p->d_ro_x, o, info, s, true)
                        : solve_mixed(p, p->d_ro_b, p->d_ro_x, o, info, s, o.precision == RP_MIXED, true);
     // the solvers leave an iterate in x on these outcomes; on the others they

@@ -208,6 +208,8 @@ struct rp_plan {
     double* d_ro_dinv64 = nullptr;     // [n_rows]
     float* d_ro_dinv32 = nullptr;      // [n_rows]
     double *d_ro_b = nullptr, *d_ro_x = nullptr;  // [n_rows] b and x in solve order
+    double* d_ro_valT = nullptr;       // [nnz + SPMV_PAD] A^T's values in solve order (first transposed solve)
+    int64_t ro_valT_version = -1;      // values_version d_ro_valT was gathered from
     std::vector<int32_t> h_ro_perm;
     int64_t ro_version = -1;           // values_version the solve-order values were gathered from
 
@@ -265,7 +267,7 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
 // reliable = true: FP32 PCG with FP64 residual replacement (RP_MIXED);
 // false: restarted FP32 inner PCG under FP64 refinement (RP_MIXED_IR)
 int solve_bicgstab(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
-                   hipStream_t s);
+                   hipStream_t s, bool ordered = false);
 int build_transpose(rp_plan* p, hipStream_t s);
 int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
                 hipStream_t s, bool reliable, bool ordered = false);
@@ -273,7 +275,7 @@ int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, 
 // reverse Cuthill-McKee order of a structurally symmetric pattern: perm[k] = row at position k
 std::vector<int32_t> rcm_order(int32_t n, const int32_t* row_ptr, const int32_t* col);
 int order_build(rp_plan* p);
-// CG / mixed solve on the solve-order copy; b and x in fused order
+// CG / mixed / BiCGStab solve on the solve-order copy; b and x in fused order
 int solve_in_order(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
                    hipStream_t s);
 // grad.hip

@@ -137,16 +137,40 @@ def test_graph_replay_in_rcm_order():
     plan.close()
 
 
-def test_bicgstab_and_rejections_in_rcm_order():
-    """BiCGStab keeps the fused order; bad modes are refused."""
-    w, m, val64, plan = _setup("ragged_rcb7")
-    update(plan, share_values(w))
-    b = w.rhs()
-    xf, _ = plan.solve(dev_tensor(b), tol=1e-10, method="bicgstab")
+@pytest.mark.parametrize("transpose", [0, 1])
+def test_bicgstab_in_rcm_order_matches_oracle(transpose):
+    """Non-symmetric (convection-diffusion) values on a scrambled mesh:
+    BiCGStab on the solve order, plain and transposed, against the oracle's
+    BiCGStab on the fused system (or its explicit transpose)."""
+    w = CASES["stretched"]()
+    v = w.momentum_values(pe=4.0, sigma=1.0)
+    m = oracle.merge(w.part.n_cells, 0, w.n_ranks, share_ranks(w))
+    vals = share_values(w, values=v)
+    val64, *_ = oracle.update(m, oracle.receive_buffer(vals))
+    plan = make_plan(w)
     plan.set_solve_order(1)
-    xo, io = plan.solve(dev_tensor(b), tol=1e-10, method="bicgstab")
-    assert_bits_equal(xo.cpu().numpy(), xf.cpu().numpy(), "BiCGStab ignores the solve order")
+    update(plan, vals, lower=True)
+    A = sp.csr_matrix((val64, m.col, m.row_ptr), shape=(m.n_rows,) * 2)
+    if transpose:
+        A = A.T.tocsr()
+        A.sort_indices()
+    b = w.rhs()
+    x_or, st, *_ = oracle.bicgstab_csr(A.indptr, A.indices, A.data, b, tol=1e-8)
+    assert st == 0
+    x, info = plan.solve(dev_tensor(b), tol=1e-8, method="bicgstab", transpose=transpose)
+    xh = x.cpu().numpy()
+    rr = np.linalg.norm(b - A @ xh) / np.linalg.norm(b)
+    assert info["status"] == 0 and rr <= 1e-8 * (1 + 1e-6), (info, rr)
+    assert np.linalg.norm(xh - x_or) <= 1e-6 * np.linalg.norm(x_or)
+    plan.close()
+
+
+def test_bad_solve_order_is_refused():
+    w, m, val64, plan = _setup("ragged_rcb7")
     import paper_2510_08536_amd.rp as low
     with pytest.raises(low.RpError):
         plan.set_solve_order(2)
+    with pytest.raises(low.RpError):
+        plan.set_solve_order(-1)
+    assert plan.solve_order() == (0, None)
     plan.close()
