@@ -200,7 +200,7 @@ cg_update_r(int32_t n, int32_t k_arg, int32_t g_spmv, T* __restrict__ r, const T
     int32_t i = blockIdx.x * VEC_BLOCK + threadIdx.x;
     // U of the thread's grid-stride elements per trip, all loads first; the
     // sums take the elements in the plain loop's order
-    constexpr int U = vec_unroll<T>();
+    constexpr int U = vec_unroll_r<T>();
     for (; (int64_t)i + (int64_t)(U - 1) * di < n; i += U * di) {
         T rv[U], qv[U], dv[U];
 #pragma unroll
@@ -278,7 +278,7 @@ cg_update_xp(int32_t n, int32_t k_arg, int32_t g_vec, int32_t resume, const T* _
         for (int32_t i = i0; i < n; i += di) p[i] = dinv[i] * r[i] + beta * p[i];
     } else {
         int32_t i = i0;
-        constexpr int U = vec_unroll<T>();
+        constexpr int U = vec_unroll_xp<T>();
         for (; (int64_t)i + (int64_t)(U - 1) * di < n; i += U * di) {
             T rv[U], dv[U], xv[U], pv[U];
 #pragma unroll

@@ -100,10 +100,12 @@ constexpr int SPMV_CAP = SPMV_UNROLL * SPMV_BLOCK;
 constexpr int SPMV_PAD = 4;                   // zeroed col / val elements past the end (pack loads)
 constexpr int GOI_KMAX = 16;                  // offsets per offset-coded SpMV group (mask width)
 constexpr int VEC_BLOCK = 256;                // elementwise kernels
-// grid-stride elements a thread of K2/K3 loads per trip (measured best:
-// 4 for FP64, 2 for FP32)
+// grid-stride elements a thread of K2 (r update) / K3 (x, p update) loads
+// per trip, measured best per kernel on MI355X: 4 / 4 for FP64, 2 / 1 for FP32
 template <typename T>
-constexpr int vec_unroll() { return sizeof(T) == 8 ? 4 : 2; }
+constexpr int vec_unroll_r() { return sizeof(T) == 8 ? 4 : 2; }
+template <typename T>
+constexpr int vec_unroll_xp() { return sizeof(T) == 8 ? 4 : 1; }
 constexpr int N_XCD = 8;                      // MI355X: 8 accelerator dies
 
 // ---------------------------------------------------------------------------

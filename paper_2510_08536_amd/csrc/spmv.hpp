@@ -36,6 +36,13 @@
 // columns are read from global memory.  On MI355X the direct loads measured
 // faster (the HBM bytes are the same; the staging costs LDS, a barrier and
 // occupancy), hence the default.  The arithmetic is the same either way.
+//
+// Coded groups stage their values in LDS straight from memory (16-byte
+// packs).  In FP64 they also stage the diagonal window x[r0 - 64, r0 + 320)
+// for the taps within +-64 rows, and hold the x of only 8 taps in registers
+// at a time (a 9th to 16th offset is summed after the first 8, in the same
+// order), which keeps 7 waves per SIMD instead of 6.  FP32 measured faster
+// without either and takes all 16 taps from memory in one pass.
 #pragma once
 
 #include "device_util.hpp"
