@@ -85,7 +85,9 @@ std::vector<int32_t> rcm_order(int32_t n, const int32_t* row_ptr, const int32_t*
     comp.reserve(n);
     int32_t stamp = 0;
     auto deg = [&](int32_t i) { return row_ptr[i + 1] - row_ptr[i]; };
-    auto bfs = [&](int32_t root) {
+    // sorted: visit each row's new neighbours by ascending degree (the final
+    // sweep); the pseudo-peripheral search needs only the levels
+    auto bfs = [&](int32_t root, bool sorted) {
         ++stamp;
         comp.clear();
         comp.push_back(root);
@@ -101,9 +103,10 @@ std::vector<int32_t> rcm_order(int32_t n, const int32_t* row_ptr, const int32_t*
                     nb.push_back(v);
                 }
             }
-            std::sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) {
-                return deg(a) != deg(b) ? deg(a) < deg(b) : a < b;
-            });
+            if (sorted)
+                std::sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) {
+                    return deg(a) != deg(b) ? deg(a) < deg(b) : a < b;
+                });
             for (int32_t v : nb) {
                 level[v] = level[u] + 1;
                 comp.push_back(v);
@@ -114,7 +117,7 @@ std::vector<int32_t> rcm_order(int32_t n, const int32_t* row_ptr, const int32_t*
         if (placed[s0]) continue;
         int32_t root = s0, depth = -1;
         for (int sweep = 0; sweep < 8; ++sweep) {
-            bfs(root);
+            bfs(root, false);
             const int32_t d = level[comp.back()];
             if (d <= depth) break;
             depth = d;
@@ -125,7 +128,7 @@ std::vector<int32_t> rcm_order(int32_t n, const int32_t* row_ptr, const int32_t*
             }
             root = best;
         }
-        bfs(root);
+        bfs(root, true);
         for (int32_t v : comp) {
             placed[v] = 1;
             order.push_back(v);
