@@ -69,7 +69,7 @@ def profiled_traffic(config):
     if not m:
         return None
     h = hashlib.sha256()
-    for f in ("spmv.hpp", "cg.hip"):
+    for f in ("spmv.hpp", "cg.hip", "rp_internal.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2510_08536_amd", "csrc", f), "rb").read())
     return int(m.group(1)) if h.hexdigest()[:16] == m.group(2) else None
 

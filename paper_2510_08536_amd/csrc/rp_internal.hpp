@@ -232,6 +232,11 @@ namespace rp {
 constexpr int SPMV_GRID_MAX = 1536;
 inline int spmv_grid(int64_t n_rows) {
     int64_t groups = (n_rows + SPMV_BLOCK - 1) / SPMV_BLOCK;
+    // more groups than the cap: the fewest groups per block the cap allows,
+    // on just enough blocks that every block gets that many (no short last
+    // round on a fraction of the grid)
+    const int64_t rounds = (groups + SPMV_GRID_MAX - 1) / SPMV_GRID_MAX;
+    if (rounds > 1) groups = (groups + rounds - 1) / rounds;
     int64_t g = ((groups + N_XCD - 1) / N_XCD) * N_XCD;
     if (g < N_XCD) g = N_XCD;
     if (g > SPMV_GRID_MAX) g = SPMV_GRID_MAX;
