@@ -243,7 +243,7 @@ inline int spmv_grid(int64_t n_rows) {
     return (int)g;
 }
 // elementwise kernels: grid-stride loops over at most VEC_GRID_MAX blocks
-constexpr int VEC_GRID_MAX = 1024;
+constexpr int VEC_GRID_MAX = 1024;  // 512 and 2048 measured slower for K2/K3
 inline int vec_grid(int64_t n) {
     int64_t g = (n + VEC_BLOCK * 4 - 1) / (VEC_BLOCK * 4);
     if (g < 1) g = 1;
