@@ -44,12 +44,12 @@ residual_kernel(int32_t n, SpmvIdx ix, const T* __restrict__ val, T* __restrict_
     __shared__ T xs[XZERO ? 1 : XWinSize<NW>::value];
     __shared__ T red[SPMV_BLOCK / 64];
     T prr = T(0), pbb = T(0);
-    const GroupRange gr = block_groups(n);
+    GroupRange gr = block_groups(ix, n);
     for (int32_t g = gr.g0; g < gr.n_groups; g += gr.step) {
         const int32_t r0 = g * SPMV_BLOCK;
         const int32_t nr = min(SPMV_BLOCK, n - r0);
         T s = T(0);
-        if (!XZERO) s = spmv_group_row<T, NW>(ix, val, x, n, g, nr, w, xs, lds).s;
+        if (!XZERO) s = spmv_group_row<T, NW>(ix, val, x, n, g, nr, w, xs, lds, gr).s;
         if ((int32_t)threadIdx.x < nr) {
             const int32_t i = r0 + threadIdx.x;
             const T bi = b[i];
@@ -154,11 +154,11 @@ cg_spmv_pq(int32_t n, SpmvIdx ix, const T* __restrict__ val, const T* __restrict
     __shared__ T xs[XWinSize<NW>::value];
     __shared__ T red[SPMV_BLOCK / 64];
     T ppq = T(0);
-    const GroupRange gr = block_groups(n);
+    GroupRange gr = block_groups(ix, n);
     for (int32_t g = gr.g0; g < gr.n_groups; g += gr.step) {
         const int32_t r0 = g * SPMV_BLOCK;
         const int32_t nr = min(SPMV_BLOCK, n - r0);
-        const GroupRow<T> gr_ = spmv_group_row<T, NW>(ix, val, p, n, g, nr, w, xs, lds);
+        const GroupRow<T> gr_ = spmv_group_row<T, NW>(ix, val, p, n, g, nr, w, xs, lds, gr);
         if ((int32_t)threadIdx.x < nr) {
             const int32_t i = r0 + threadIdx.x;
             q[i] = gr_.s;
@@ -799,11 +799,11 @@ bi_spmv_rv(int32_t n, SpmvIdx ix, const double* __restrict__ val, const double* 
     __shared__ double xs[XWinSize<NW>::value];
     __shared__ double red[SPMV_BLOCK / 64];
     double prv = 0.0;
-    const GroupRange gr = block_groups(n);
+    GroupRange gr = block_groups(ix, n);
     for (int32_t g = gr.g0; g < gr.n_groups; g += gr.step) {
         const int32_t r0 = g * SPMV_BLOCK;
         const int32_t nr = min(SPMV_BLOCK, n - r0);
-        const GroupRow<double> gr_ = spmv_group_row<double, NW>(ix, val, y, n, g, nr, w, xs, lds);
+        const GroupRow<double> gr_ = spmv_group_row<double, NW>(ix, val, y, n, g, nr, w, xs, lds, gr);
         if ((int32_t)threadIdx.x < nr) {
             const int32_t i = r0 + threadIdx.x;
             v[i] = gr_.s;
@@ -864,11 +864,11 @@ bi_spmv_ts(int32_t n, int32_t g_vec, SpmvIdx ix, const double* __restrict__ val,
         return;
     }
     double pts = 0.0, ptt = 0.0;
-    const GroupRange gr = block_groups(n);
+    GroupRange gr = block_groups(ix, n);
     for (int32_t g = gr.g0; g < gr.n_groups; g += gr.step) {
         const int32_t r0 = g * SPMV_BLOCK;
         const int32_t nr = min(SPMV_BLOCK, n - r0);
-        const GroupRow<double> gr_ = spmv_group_row<double, NW>(ix, val, z, n, g, nr, w, xs, lds);
+        const GroupRow<double> gr_ = spmv_group_row<double, NW>(ix, val, z, n, g, nr, w, xs, lds, gr);
         if ((int32_t)threadIdx.x < nr) {
             const int32_t i = r0 + threadIdx.x;
             t[i] = gr_.s;

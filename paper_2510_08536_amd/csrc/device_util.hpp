@@ -51,6 +51,16 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
 // Remapping b to (b % 8) * per + b / 8 makes the logical blocks of one XCD
 // consecutive, so neighbouring row groups (and the x entries they share) are
 // worked on by one XCD and its L2.  gridDim.x must be a multiple of 8.
+// Barrier for hand-offs through LDS only.  __syncthreads fences global
+// memory too, which makes every wave wait for all of its outstanding global
+// loads at the barrier; this one waits only for the wave's LDS (and scalar)
+// accesses, so global loads issued before it stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ int32_t xcd_block() {
     const int32_t per = (int32_t)(gridDim.x / N_XCD);
     return (int32_t)(blockIdx.x % N_XCD) * per + (int32_t)(blockIdx.x / N_XCD);

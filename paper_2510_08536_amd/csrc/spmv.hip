@@ -9,11 +9,11 @@ spmv_kernel(int32_t n_rows, SpmvIdx ix, const T* __restrict__ val, const T* __re
             XWin w) {
     __shared__ __align__(16) T lds[SPMV_CAP];
     __shared__ T xs[XWinSize<NW>::value];
-    const GroupRange gr = block_groups(n_rows);
+    GroupRange gr = block_groups(ix, n_rows);
     for (int32_t g = gr.g0; g < gr.n_groups; g += gr.step) {
         const int32_t r0 = g * SPMV_BLOCK;
         const int32_t nr = min(SPMV_BLOCK, n_rows - r0);
-        const GroupRow<T> gr_ = spmv_group_row<T, NW>(ix, val, x, n_rows, g, nr, w, xs, lds);
+        const GroupRow<T> gr_ = spmv_group_row<T, NW>(ix, val, x, n_rows, g, nr, w, xs, lds, gr);
         if ((int32_t)threadIdx.x < nr) y[r0 + threadIdx.x] = gr_.s;
     }
 }

@@ -42,7 +42,10 @@
 // for the taps within +-64 rows, and hold the x of only 8 taps in registers
 // at a time (a 9th to 16th offset is summed after the first 8, in the same
 // order), which keeps 7 waves per SIMD instead of 6.  FP32 measured faster
-// without either and takes all 16 taps from memory in one pass.
+// without either and takes all 16 taps from memory in one pass.  Both
+// precisions load the next group's metadata (offset table, value stretch,
+// masks) while the current group's values load, and hand LDS over with
+// barriers that do not wait for global loads (lds_barrier).
 #pragma once
 
 #include "device_util.hpp"
@@ -231,28 +234,71 @@ __device__ __forceinline__ T spmv_group_csr(const int32_t* __restrict__ row_ptr,
     return s;
 }
 
+// Metadata of one offset-coded group: its offset count K (0: a CSR group)
+// and offset table, its value stretch [base, end), and the thread's row mask.
+// The kernels load it one group ahead (spmv_group_row).
+struct CodedMeta {
+    int32_t K, base, end;
+    uint32_t m;
+    int32_t off[GOI_KMAX];
+};
+
+// The group-uniform parts are read through the constant address space, so
+// they are scalar loads into scalar registers (the index arrays are not
+// written while an SpMV runs); the mask is a vector load.
+typedef const __attribute__((address_space(4))) int32_t* ConstI32;
+
+__device__ __forceinline__ void coded_meta_load(const SpmvIdx& ix, int32_t g, int32_t n, CodedMeta& c) {
+    const int32_t r0 = g * SPMV_BLOCK, nr = min(SPMV_BLOCK, n - r0);
+    c.K = ((ConstI32)ix.goi_k)[g];
+    const ConstI32 off = (ConstI32)ix.goi_off + (int64_t)g * GOI_KMAX;
+#pragma unroll
+    for (int j = 0; j < GOI_KMAX; ++j) c.off[j] = off[j];
+    c.base = ((ConstI32)ix.row_ptr)[r0];
+    c.end = ((ConstI32)ix.row_ptr)[r0 + nr];
+    c.m = (int32_t)threadIdx.x < nr ? (uint32_t)ix.goi_mask[r0 + threadIdx.x] : 0u;
+}
+
+// Row groups of block L (after xcd_block()) in a grid of G blocks: L, L + G,
+// L + 2G, ...  At any moment the whole chip works on one window of G
+// consecutive groups, and each XCD on a contiguous eighth of it.
+// meta: the first group's coded metadata, when the plan has coded groups.
+struct GroupRange {
+    int32_t g0, n_groups, step;
+    CodedMeta meta;
+};
+__device__ __forceinline__ GroupRange block_groups(const SpmvIdx& ix, int32_t n_rows) {
+    GroupRange r;
+    r.n_groups = (int32_t)(((int64_t)n_rows + SPMV_BLOCK - 1) / SPMV_BLOCK);
+    r.g0 = xcd_block();
+    r.step = (int32_t)gridDim.x;
+    r.meta.K = 0;
+    if (ix.goi_k != nullptr && r.g0 < r.n_groups) coded_meta_load(ix, r.g0, n_rows, r.meta);
+    return r;
+}
+
 // Offset-coded group g (K offsets): row sum for row r0 + threadIdx.x.
 // lds: SPMV_CAP elements, 16-byte aligned.  The group's values are read as
 // aligned 16-byte packs (2 doubles or 4 floats); when the plan is built, a
 // group is coded only if its packs fit SPMV_CAP elements in both precisions.
 template <typename T>
 __device__ __forceinline__ GroupRow<T> spmv_group_coded(const SpmvIdx& ix, const T* __restrict__ val,
-                                                      const T* __restrict__ x, int32_t n, int32_t g,
-                                                      int32_t K, int32_t r0, int32_t nr, T* lds) {
+                                                      const T* __restrict__ x, int32_t n, int32_t r0,
+                                                      int32_t nr, T* lds, CodedMeta& meta, int32_t g_next) {
 #pragma clang fp contract(off)
     typedef typename Pack<T>::type VP;
     constexpr int E = Pack<T>::E;
     __shared__ int32_t wtot[SPMV_BLOCK / 64];
     const int t = threadIdx.x;
+    // this group's metadata (loaded during the previous group)
+    const int32_t K = meta.K, base = meta.base, end = meta.end;
+    const uint32_t m = meta.m;
     int32_t off[GOI_KMAX];
 #pragma unroll
-    for (int j = 0; j < GOI_KMAX; ++j) off[j] = ix.goi_off[(int64_t)g * GOI_KMAX + j];
-    const int32_t base = ix.row_ptr[r0];
-    const int32_t end = ix.row_ptr[r0 + nr];
+    for (int j = 0; j < GOI_KMAX; ++j) off[j] = meta.off[j];
     const int32_t al = base & ~(E - 1);            // packs start on a multiple of E
     const int32_t npk = (end - al + E - 1) / E;
     const int32_t last = npk > 0 ? npk - 1 : 0;
-    const uint32_t m = t < nr ? (uint32_t)ix.goi_mask[r0 + t] : 0u;
     // FP64: the block's diagonal window x[r0 - XN, r0 + SPMV_BLOCK + XN) goes
     // to LDS, and taps with |offset| <= XN read it there instead of memory.
     // (FP32 runs slower with it and takes every tap from memory.)
@@ -265,7 +311,11 @@ __device__ __forceinline__ GroupRow<T> spmv_group_coded(const SpmvIdx& ix, const
         if (e0 >= 0 && e0 < n) xa = x[e0];
         if (t < 2 * XN && e1 < n) xb = x[e1];
     }
-    __syncthreads();  // the previous group's LDS reads are done before any load lands there
+    // the previous group's LDS reads are done before any load lands there
+    // (global loads, such as the window's, stay in flight)
+    lds_barrier();
+    // the next group's metadata, in flight while this group's values load
+    if (g_next >= 0) coded_meta_load(ix, g_next, n, meta);
     // the row's first entry: exclusive prefix of the row lengths (popcounts)
     const int32_t c = __popc(m);
     const int32_t inc = wave_incl_scan(c);
@@ -302,7 +352,7 @@ __device__ __forceinline__ GroupRow<T> spmv_group_coded(const SpmvIdx& ix, const
     // the packs of every wave must be in LDS before any wave reads them: wait
     // for all of this wave's loads, then the barrier
     __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    lds_barrier();
     if constexpr (XWIN) {
 #pragma unroll
         for (int j = 0; j < KH; ++j)
@@ -339,14 +389,19 @@ __device__ __forceinline__ GroupRow<T> spmv_group_coded(const SpmvIdx& ix, const
 }
 
 // Row sum of row g * SPMV_BLOCK + threadIdx.x in the form chosen for group g.
+// gr carries the coded groups' metadata one group ahead: gr.meta describes
+// group g on entry and group g + gr.step on return.
 template <typename T, int NW>
 __device__ __forceinline__ GroupRow<T> spmv_group_row(const SpmvIdx& ix, const T* __restrict__ val,
                                                      const T* __restrict__ x, int32_t n, int32_t g, int32_t nr,
-                                                     const XWin& w, T* xs, T* lds) {
+                                                     const XWin& w, T* xs, T* lds, GroupRange& gr) {
     const int32_t r0 = g * SPMV_BLOCK;
     if (ix.goi_k != nullptr) {
-        const int32_t K = ix.goi_k[g];
-        if (K > 0) return spmv_group_coded<T>(ix, val, x, n, g, K, r0, nr, lds);
+        const int32_t g_next = g + gr.step < gr.n_groups ? g + gr.step : -1;
+        if (gr.meta.K > 0) return spmv_group_coded<T>(ix, val, x, n, r0, nr, lds, gr.meta, g_next);
+        const T s = spmv_group_csr<T, NW>(ix.row_ptr, ix.col, val, x, n, r0, nr, w, xs, lds);
+        if (g_next >= 0) coded_meta_load(ix, g_next, n, gr.meta);
+        return GroupRow<T>{s, false, T(0)};
     }
     return GroupRow<T>{spmv_group_csr<T, NW>(ix.row_ptr, ix.col, val, x, n, r0, nr, w, xs, lds), false, T(0)};
 }
@@ -360,19 +415,6 @@ __device__ __forceinline__ T own_x(int32_t i, const GroupRow<T>& gr, const T* xs
     return x[i];
 }
 
-// Row groups of block L (after xcd_block()) in a grid of G blocks: L, L + G,
-// L + 2G, ...  At any moment the whole chip works on one window of G
-// consecutive groups, and each XCD on a contiguous eighth of it.
-struct GroupRange {
-    int32_t g0, n_groups, step;
-};
-__device__ __forceinline__ GroupRange block_groups(int32_t n_rows) {
-    GroupRange r;
-    r.n_groups = (int32_t)(((int64_t)n_rows + SPMV_BLOCK - 1) / SPMV_BLOCK);
-    r.g0 = xcd_block();
-    r.step = (int32_t)gridDim.x;
-    return r;
-}
 
 // Expand CALL(NW) for the plan's window mode.
 #define RP_DISPATCH_NW(nw, CALL)  \
