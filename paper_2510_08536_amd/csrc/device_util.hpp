@@ -46,11 +46,6 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
     return s;
 }
 
-// ---- XCD-aware block order -----------------------------------------------
-// Workgroups are handed to the 8 XCDs round-robin (block b -> XCD b % 8).
-// Remapping b to (b % 8) * per + b / 8 makes the logical blocks of one XCD
-// consecutive, so neighbouring row groups (and the x entries they share) are
-// worked on by one XCD and its L2.  gridDim.x must be a multiple of 8.
 // Barrier for hand-offs through LDS only.  __syncthreads fences global
 // memory too, which makes every wave wait for all of its outstanding global
 // loads at the barrier; this one waits only for the wave's LDS (and scalar)
@@ -61,6 +56,11 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// ---- XCD-aware block order -----------------------------------------------
+// Workgroups are handed to the 8 XCDs round-robin (block b -> XCD b % 8).
+// Remapping b to (b % 8) * per + b / 8 makes the logical blocks of one XCD
+// consecutive, so neighbouring row groups (and the x entries they share) are
+// worked on by one XCD and its L2.  gridDim.x must be a multiple of 8.
 __device__ __forceinline__ int32_t xcd_block() {
     const int32_t per = (int32_t)(gridDim.x / N_XCD);
     return (int32_t)(blockIdx.x % N_XCD) * per + (int32_t)(blockIdx.x / N_XCD);
