@@ -87,8 +87,8 @@ def cpu_model():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
-              "the multi-GPU split is a design note, not part of it", file=sys.stderr)
+        print(f"bench.py: the library runs one plan on one GPU (asked for --gpus {a.gpus}); "
+              "splitting the ranks over several GPUs is described, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
