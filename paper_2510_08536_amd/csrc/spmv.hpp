@@ -43,7 +43,7 @@
 // at a time (a 9th to 16th offset is summed after the first 8, in the same
 // order), which keeps 7 waves per SIMD instead of 6.  FP32 measured faster
 // without either and takes all 16 taps from memory in one pass.  Both
-// precisions load the next group's metadata (offset table, value stretch,
+// precisions load the next group's metadata (offset count, value stretch,
 // masks) while the current group's values load, and hand LDS over with
 // barriers that do not wait for global loads (lds_barrier).
 #pragma once
@@ -234,16 +234,17 @@ __device__ __forceinline__ T spmv_group_csr(const int32_t* __restrict__ row_ptr,
     return s;
 }
 
-// Metadata of one offset-coded group: its offset count K (0: a CSR group)
-// and offset table, its value stretch [base, end), and the thread's row mask.
-// The kernels load it one group ahead (spmv_group_row).
+// Metadata of one offset-coded group: its offset count K (0: a CSR group),
+// its value stretch [base, end), and the thread's row mask.  The kernels load
+// it one group ahead (spmv_group_row).  The offset table is not part of it:
+// held a group ahead it cost enough scalar registers to spill them, and the
+// SpMV measured slower than with the table loaded when the group starts.
 struct CodedMeta {
     int32_t K, base, end;
     uint32_t m;
-    int32_t off[GOI_KMAX];
 };
 
-// The group-uniform parts are read through the constant address space, so
+// The group-uniform values are read through the constant address space, so
 // they are scalar loads into scalar registers (the index arrays are not
 // written while an SpMV runs); the mask is a vector load.
 typedef const __attribute__((address_space(4))) int32_t* ConstI32;
@@ -251,9 +252,6 @@ typedef const __attribute__((address_space(4))) int32_t* ConstI32;
 __device__ __forceinline__ void coded_meta_load(const SpmvIdx& ix, int32_t g, int32_t n, CodedMeta& c) {
     const int32_t r0 = g * SPMV_BLOCK, nr = min(SPMV_BLOCK, n - r0);
     c.K = ((ConstI32)ix.goi_k)[g];
-    const ConstI32 off = (ConstI32)ix.goi_off + (int64_t)g * GOI_KMAX;
-#pragma unroll
-    for (int j = 0; j < GOI_KMAX; ++j) c.off[j] = off[j];
     c.base = ((ConstI32)ix.row_ptr)[r0];
     c.end = ((ConstI32)ix.row_ptr)[r0 + nr];
     c.m = (int32_t)threadIdx.x < nr ? (uint32_t)ix.goi_mask[r0 + threadIdx.x] : 0u;
@@ -290,12 +288,13 @@ __device__ __forceinline__ GroupRow<T> spmv_group_coded(const SpmvIdx& ix, const
     constexpr int E = Pack<T>::E;
     __shared__ int32_t wtot[SPMV_BLOCK / 64];
     const int t = threadIdx.x;
-    // this group's metadata (loaded during the previous group)
+    // this group's metadata (loaded during the previous group) and offset table
     const int32_t K = meta.K, base = meta.base, end = meta.end;
     const uint32_t m = meta.m;
     int32_t off[GOI_KMAX];
+    const ConstI32 offp = (ConstI32)ix.goi_off + (int64_t)(r0 / SPMV_BLOCK) * GOI_KMAX;
 #pragma unroll
-    for (int j = 0; j < GOI_KMAX; ++j) off[j] = meta.off[j];
+    for (int j = 0; j < GOI_KMAX; ++j) off[j] = offp[j];
     const int32_t al = base & ~(E - 1);            // packs start on a multiple of E
     const int32_t npk = (end - al + E - 1) / E;
     const int32_t last = npk > 0 ? npk - 1 : 0;
