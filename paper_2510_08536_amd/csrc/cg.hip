@@ -198,30 +198,36 @@ cg_update_r(int32_t n, int32_t k_arg, int32_t g_spmv, T* __restrict__ r, const T
     T prz = T(0), prr = T(0);
     const int32_t di = gridDim.x * VEC_BLOCK;
     int32_t i = blockIdx.x * VEC_BLOCK + threadIdx.x;
-    // U of the thread's grid-stride elements per trip, all loads first; the
-    // sums take the elements in the plain loop's order
+    // K2 sweeps the rows from the top down (element e = n - 1 - i), K1 and K3
+    // from the bottom up: each kernel then starts on the lines its
+    // predecessor touched last, which are still in the 256 MB memory-side
+    // cache.  U of the thread's grid-stride elements per trip, all loads
+    // first; the sums take the elements in the loop's order.
     constexpr int U = vec_unroll_r<T>();
     for (; (int64_t)i + (int64_t)(U - 1) * di < n; i += U * di) {
         T rv[U], qv[U], dv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            rv[u] = r[i + u * di];
-            qv[u] = q[i + u * di];
-            dv[u] = dinv[i + u * di];
+            const int32_t e = n - 1 - (i + u * di);
+            rv[u] = r[e];
+            qv[u] = q[e];
+            dv[u] = dinv[e];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            const int32_t e = n - 1 - (i + u * di);
             const T ri = rv[u] - a * qv[u];
-            r[i + u * di] = ri;
+            r[e] = ri;
             const T zi = dv[u] * ri;
             prz += ri * zi;
             prr += ri * ri;
         }
     }
     for (; i < n; i += di) {
-        const T ri = r[i] - a * q[i];
-        r[i] = ri;
-        const T zi = dinv[i] * ri;
+        const int32_t e = n - 1 - i;
+        const T ri = r[e] - a * q[e];
+        r[e] = ri;
+        const T zi = dinv[e] * ri;
         prz += ri * zi;
         prr += ri * ri;
     }
@@ -832,10 +838,14 @@ bi_half(int32_t n, int32_t k, int32_t g_spmv, const double* __restrict__ r, cons
     }
     const double a = st->rho[k & 3] / rv;
     double pss = 0.0;
+    // top down (e = n - 1 - i), like bi_update: the SpMVs and bi_direction
+    // sweep bottom up, so each kernel starts on its predecessor's most recent
+    // lines (still in the memory-side cache)
     for (int32_t i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK) {
-        const double si = r[i] - a * v[i];
-        s[i] = si;
-        z[i] = dinv[i] * si;
+        const int32_t e = n - 1 - i;
+        const double si = r[e] - a * v[e];
+        s[e] = si;
+        z[e] = dinv[e] * si;
         pss += si * si;
     }
     const double b = block_sum<double, VEC_BLOCK>(pss, red);
@@ -917,12 +927,13 @@ bi_update(int32_t n, int32_t k, int32_t g_spmv, double* __restrict__ x, const do
     }
     const double omega = ts / tt;
     double prho = 0.0, prr = 0.0;
-    for (int32_t i = i0; i < n; i += di) {
-        const double xi = (x[i] + a * y[i]) + omega * z[i];
-        const double ri = s[i] - omega * t[i];
-        x[i] = xi;
-        r[i] = ri;
-        prho += rh[i] * ri;
+    for (int32_t i = i0; i < n; i += di) {  // top down, see bi_half
+        const int32_t e = n - 1 - i;
+        const double xi = (x[e] + a * y[e]) + omega * z[e];
+        const double ri = s[e] - omega * t[e];
+        x[e] = xi;
+        r[e] = ri;
+        prho += rh[e] * ri;
         prr += ri * ri;
     }
     const double b1 = block_sum<double, VEC_BLOCK>(prho, red);
