@@ -64,9 +64,11 @@ extern "C" {
 
 /* ---- precisions -------------------------------------------------------- */
 #define RP_FP64 0                 /* FP64 everywhere */
-#define RP_MIXED 1                /* FP32 PCG with FP64 residual-replacement updates (solve only) */
+#define RP_MIXED 1                /* mixed-precision iterative refinement (solve only): FP64
+                                     residual and solution, FP32 inner PCG to inner_tol */
 #define RP_FP32 2                 /* FP32 matrix and vectors (rp_spmv only) */
-#define RP_MIXED_IR 3             /* FP32 inner PCG restarted under FP64 refinement (solve only) */
+#define RP_MIXED_RR 3             /* FP32 PCG with FP64 residual replacement every
+                                     update_delta reduction (solve only) */
 
 /* ---- Krylov methods ------------------------------------------------------ */
 #define RP_CG 0                   /* Jacobi-PCG, symmetric positive definite A (the pressure
@@ -92,11 +94,12 @@ typedef struct rp_rank_desc {
 
 typedef struct rp_solve_opts {
     double tol;              /* stop when ||b - A x||_2 <= tol ||b||_2 (default 1e-8) */
-    double inner_tol;        /* RP_MIXED_IR: inner FP32 relative tolerance (default 1e-4) */
-    double update_delta;     /* RP_MIXED: the FP64 update is due once the FP32 residual has
+    double inner_tol;        /* RP_MIXED: each inner FP32 PCG stops at this relative
+                                residual (default 1e-4) */
+    double update_delta;     /* RP_MIXED_RR: the FP64 update is due once the FP32 residual has
                                 fallen by this factor since the last one (default 0.1) */
     int32_t max_iter;        /* FP64: CG iterations; mixed: total FP32 iterations */
-    int32_t precision;       /* RP_FP64, RP_MIXED or RP_MIXED_IR */
+    int32_t precision;       /* RP_FP64, RP_MIXED or RP_MIXED_RR */
     int32_t max_outer;       /* mixed: FP64 residual updates / refinement steps (default 200) */
     int32_t check_every;     /* host reads the device convergence state every this
                                 many iterations (default 32); iteration counts do
@@ -150,6 +153,25 @@ int rp_plan_sizes(const rp_plan* plan, int64_t* n_rows, int64_t* nnz_local,
  * column ids, int64). */
 int rp_plan_get_csr(rp_plan* plan, int32_t* row_ptr, int32_t* col, int32_t* perm,
                     int32_t* nl_row_ptr, int64_t* nl_col);
+
+/* Device pointers to the plan's pattern and current values, valid until
+ * rp_plan_destroy and read-only for the caller.  The arrays keep the layouts
+ * of rp_plan_get_csr and rp_plan_get_values; the values change with every
+ * update, so read them in stream order after it.  recv is the receive buffer
+ * in slot order (the update's staging area).  No device work, no sync. */
+typedef struct rp_device_ptrs {
+    const int32_t* row_ptr;     /* [n_rows+1] fused local block */
+    const int32_t* col;         /* [nnz_local] local column ids, ascending per row */
+    const int32_t* perm;        /* [n_slots] P: slot -> CSR position */
+    const int32_t* nl_row_ptr;  /* [n_rows+1] non-local block */
+    const int64_t* nl_col;      /* [nnz_nonlocal] global column ids */
+    const double* val64;        /* [n_slots] CSR order, local block then non-local */
+    const float* val32;         /* [n_slots] RNE copy of val64 */
+    const double* dinv64;       /* [n_rows] 1 / diag */
+    const float* dinv32;        /* [n_rows] RNE copy of dinv64 */
+    const double* recv;         /* [n_slots] receive buffer, slot order */
+} rp_device_ptrs;
+int rp_plan_device_ptrs(const rp_plan* plan, rp_device_ptrs* out);
 
 /* Copy the current values to caller-allocated host buffers (any may be NULL):
  * val64[n_slots], val32[n_slots] (CSR order, local block then non-local),
@@ -247,12 +269,14 @@ int rp_spmv(rp_plan* plan, int32_t precision, const void* x, void* y, void* stre
 
 /* ---- solve (Sec. 4: CG for the pressure system, BiCGStab for momentum) -- *
  * opts->method = RP_CG (default): RP_FP64 is Jacobi-PCG in FP64.  RP_MIXED
- * runs the same PCG in FP32 (FP32 matrix, preconditioner, vectors and dot
- * products) and, whenever its
- * residual has fallen by update_delta, folds its correction into the FP64
- * solution and replaces its residual by the FP64 residual b - A x, keeping
- * the search direction; the stop test is on that FP64 residual.  RP_MIXED_IR
- * restarts an FP32 PCG (to inner_tol) on every FP64 refinement residual.
+ * is iterative refinement: the FP64 residual r = b - A x is rounded to FP32,
+ * an FP32 Jacobi-PCG (FP32 matrix, preconditioner, vectors and dot products)
+ * solves A d = r from d = 0 until its residual is below inner_tol times its
+ * start, x += d in FP64, and this repeats until the FP64 residual meets tol.
+ * RP_MIXED_RR runs one FP32 PCG throughout and, whenever its residual has
+ * fallen by update_delta, folds its correction into the FP64 solution and
+ * replaces its residual by the FP64 residual b - A x, keeping the search
+ * direction; the stop test is on that FP64 residual.
  * opts->method = RP_BICGSTAB: BiCGStab with M = diag(A) applied on the
  * right, in FP64, for non-symmetric matrices (van der Vorst 1992; one
  * iteration = two products with A); its stop test and restart follow the
@@ -279,6 +303,14 @@ void rp_solve_opts_default(rp_solve_opts* opts);
  * gradients of a face. */
 int rp_value_grad(rp_plan* plan, const double* lambda, const double* x, double* g_slots,
                   void* stream);
+
+/* Launch shape of the solvers' elementwise kernels (a diagnostic knob; the
+ * default sizes the grid to n_rows, at most 1024 blocks).  blocks = 0 restores
+ * the default; 1..16384 fixes the grid, far beyond what the chip holds at
+ * once, so that blocks of one launch start after others have finished.
+ * Results are the same for any grid except for the rounding of dot products
+ * (one partial sum per block).  RP_ERR_ARG outside 0..16384. */
+int rp_plan_set_vec_grid(rp_plan* plan, int32_t blocks);
 
 /* ---- lifetime / diagnostics --------------------------------------------- */
 /* Wait for the plan's pending work; reports a pending RP_ERR_VALUE. */

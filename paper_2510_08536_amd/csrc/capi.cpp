@@ -364,6 +364,31 @@ int rp_plan_get_csr(rp_plan* p, int32_t* row_ptr, int32_t* col, int32_t* perm, i
     return RP_OK;
 }
 
+int rp_plan_device_ptrs(const rp_plan* p, rp_device_ptrs* out) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    RP_CHECK(out != nullptr, RP_ERR_ARG, "out is NULL");
+    out->row_ptr = p->d_row_ptr;
+    out->col = p->d_col;
+    out->perm = p->d_perm;
+    out->nl_row_ptr = p->d_nl_row_ptr;
+    out->nl_col = p->d_nl_col;
+    out->val64 = p->d_val64;
+    out->val32 = p->d_val32;
+    out->dinv64 = p->d_dinv64;
+    out->dinv32 = p->d_dinv32;
+    out->recv = p->d_recv;
+    return RP_OK;
+}
+
+int rp_plan_set_vec_grid(rp_plan* p, int32_t blocks) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    RP_CHECK(blocks >= 0 && blocks <= VEC_GRID_LIMIT, RP_ERR_ARG, "blocks must be in 0..%d", VEC_GRID_LIMIT);
+    p->vec_grid_override = blocks;
+    return RP_OK;
+}
+
 int rp_plan_get_values(rp_plan* p, double* val64, float* val32, double* dinv64, float* dinv32) {
     clear_error();
     RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
@@ -441,8 +466,8 @@ int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, 
     RP_CHECK(o.tol >= 0.0 && o.inner_tol > 0.0 && o.inner_tol < 1.0 && o.update_delta > 0.0 &&
                  o.update_delta < 1.0 && o.max_iter >= 0 && o.max_outer >= 0 && o.max_restarts >= 0,
              RP_ERR_ARG, "bad solve options");
-    RP_CHECK(o.precision == RP_FP64 || o.precision == RP_MIXED || o.precision == RP_MIXED_IR, RP_ERR_ARG,
-             "precision must be RP_FP64, RP_MIXED or RP_MIXED_IR");
+    RP_CHECK(o.precision == RP_FP64 || o.precision == RP_MIXED || o.precision == RP_MIXED_RR, RP_ERR_ARG,
+             "precision must be RP_FP64, RP_MIXED or RP_MIXED_RR");
     RP_CHECK(o.method == RP_CG || o.method == RP_BICGSTAB, RP_ERR_ARG, "method must be RP_CG or RP_BICGSTAB");
     RP_CHECK(o.method == RP_CG || o.precision == RP_FP64, RP_ERR_UNSUPPORTED, "BiCGStab runs in FP64 only");
     RP_CHECK(o.transpose == 0 || o.transpose == 1, RP_ERR_ARG, "transpose must be 0 or 1");
@@ -460,7 +485,7 @@ int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, 
     } else if (o.precision == RP_FP64) {
         rc = solve_fp64(p, b, x, o, inf, s);
     } else {
-        rc = solve_mixed(p, b, x, o, inf, s, o.precision == RP_MIXED);
+        rc = solve_mixed(p, b, x, o, inf, s, o.precision == RP_MIXED_RR);
     }
     inf.status = rc;
     return rc;

@@ -17,6 +17,16 @@
 // kernels enqueued after a stop return at entry, so the iteration count does
 // not depend on how many iterations the host enqueues per chunk.
 //
+// Ordering rule for the device state: the blocks of one launch may run in
+// any order, and a block may start after block 0 has finished.  So a field
+// that block 0 writes in a launch is read at entry by the same launch only
+// where the outcome cannot differ: the writing path does no vector work, and
+// every block reaches it from the same sums (the breakdown and stop paths of
+// K2 and of the BiCGStab kernels).  K3 still moves x on its stop path, so it
+// is gated on `kk`, which only K2 writes (the iteration K2 completed, -1 if
+// K2 did nothing); BiCGStab's last kernel gates its half step on `half_k`,
+// which only the kernel before it writes.
+//
 // Stop test: ||r||^2 <= tol^2 ||b||^2 on the recurrence residual, then
 // confirmed on b - A x; a failed confirmation restarts CG from the current x.
 #include <algorithm>
@@ -176,20 +186,27 @@ __global__ void __launch_bounds__(VEC_BLOCK)
 cg_update_r(int32_t n, int32_t k_arg, int32_t g_spmv, T* __restrict__ r, const T* __restrict__ q,
             const T* __restrict__ dinv, T* __restrict__ part, CgState<T>* st) {
 #pragma clang fp contract(off)
-    if (st->done != CG_RUNNING) return;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    // K3 runs only if kk names its iteration, so every path that does no
+    // update leaves kk = -1
+    if (st->done != CG_RUNNING) {
+        if (lead) st->kk = -1;
+        return;
+    }
     // iteration number: the argument, or (replayed graphs) the device state,
     // which only K3 and the finalize kernel write
     const int32_t k = k_arg >= 0 ? k_arg : st->iter;
     if (k >= st->max_iter) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->kk = -1;
+        if (lead) st->kk = -1;
         return;
     }
     __shared__ T red[VEC_BLOCK / 64];
     const T pq = sum_partials_all<T, VEC_BLOCK>(part + PART_A, g_spmv, red);
     if (!(pq > T(0)) || !isfinite(pq)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (lead) {
             st->pq = pq;
             st->iter = k;
+            st->kk = -1;
             st->done = CG_BREAKDOWN;
         }
         return;
@@ -236,11 +253,11 @@ cg_update_r(int32_t n, int32_t k_arg, int32_t g_spmv, T* __restrict__ r, const T
     if (threadIdx.x == 0) {
         part[PART_RZ + blockIdx.x] = b1;
         part[PART_RR + blockIdx.x] = b2;
-        if (blockIdx.x == 0) {
-            st->pq = pq;
-            st->alpha = a;
-            st->kk = k;
-        }
+    }
+    if (lead) {
+        st->pq = pq;
+        st->alpha = a;
+        st->kk = k;
     }
 }
 
@@ -248,17 +265,21 @@ cg_update_r(int32_t n, int32_t k_arg, int32_t g_spmv, T* __restrict__ r, const T
 // beta = rz_{k+1} / rz_k and p = M^-1 r + beta p.  x uses the old p, exactly
 // as if K2 had moved it.  resume: continue after the residual was replaced
 // (partials from cg_rz_rr): x already holds this iteration's step, the stop
-// tests are skipped.
+// tests are skipped.  Runs only when K2 completed this iteration (kk); block
+// 0 records a stop in `done`, which K3 itself never reads.
 template <typename T>
 __global__ void __launch_bounds__(VEC_BLOCK)
 cg_update_xp(int32_t n, int32_t k_arg, int32_t g_vec, int32_t resume, const T* __restrict__ r,
              const T* __restrict__ dinv, T* __restrict__ x, T* __restrict__ p, const T* __restrict__ part,
              CgState<T>* st) {
 #pragma clang fp contract(off)
-    if (!resume && st->done != CG_RUNNING) return;
     // iteration number: the argument, or the one K2 of this iteration wrote
-    const int32_t k = k_arg >= 0 ? k_arg : st->kk;
-    if (k < 0) return;
+    int32_t k = k_arg;
+    if (!resume) {
+        const int32_t kk = st->kk;
+        if (kk < 0 || (k_arg >= 0 && kk != k_arg)) return;
+        k = kk;
+    }
     __shared__ T red[VEC_BLOCK / 64];
     const T rz = sum_partials_all<T, VEC_BLOCK>(part + PART_RZ, g_vec, red);
     const T rr = sum_partials_all<T, VEC_BLOCK>(part + PART_RR, g_vec, red);
@@ -374,7 +395,7 @@ template <typename T>
 Cg<T> make_cg(rp_plan* p, const MatView& m, const T* val, const T* dinv, T* x, const T* b, T* r, T* pv, T* q,
               CgState<T>* st, CgState<T>* h, int kernel_id, hipStream_t s) {
     Cg<T> c{p, (int32_t)p->n_rows, m.ix, val, dinv, x, b, r, pv, q, (T*)p->d_partials, st, h,
-            kernel_id, s, spmv_grid(p->n_rows), vec_grid(p->n_rows), m.xw_mode, XWin{{p->xw_d[0], p->xw_d[1]}}};
+            kernel_id, s, spmv_grid(p->n_rows), plan_vec_grid(p), m.xw_mode, XWin{{p->xw_d[0], p->xw_d[1]}}};
     return c;
 }
 
@@ -706,7 +727,10 @@ int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, 
 //   D  stop at the half step if (s, s) is small; t = A z;    partials of (t, s), (t, t)
 //   E  omega = (t, s) / (t, t); x = (x + alpha y) + omega z; r = s - omega t;
 //      partials of (rh, r) and (r, r)
-// A half-step stop leaves BI_HALF; E then moves x by alpha y and ends.
+// A half-step stop in D of iteration k leaves done = BI_HALF and half_k = k;
+// E of iteration k then moves x by alpha y, and the solve ends there (BI_HALF
+// counts as converged).  E never writes `done` on that path, so its blocks
+// all see the same BI_HALF whatever their order.
 namespace {
 
 // rh = r, p = v = 0; partials of (rh, r) -> PART_RZ and (r, r) -> PART_RR;
@@ -858,8 +882,9 @@ bi_half(int32_t n, int32_t k, int32_t g_spmv, const double* __restrict__ r, cons
 // D: half-step stop test on (s, s); t = A z; partials of (t, s) -> PART_A, (t, t) -> PART_B
 template <int NW>
 __global__ void __launch_bounds__(SPMV_BLOCK)
-bi_spmv_ts(int32_t n, int32_t g_vec, SpmvIdx ix, const double* __restrict__ val, const double* __restrict__ z,
-           double* __restrict__ t, const double* __restrict__ s, double* __restrict__ part, BiState* st, XWin w) {
+bi_spmv_ts(int32_t n, int32_t k, int32_t g_vec, SpmvIdx ix, const double* __restrict__ val,
+           const double* __restrict__ z, double* __restrict__ t, const double* __restrict__ s,
+           double* __restrict__ part, BiState* st, XWin w) {
 #pragma clang fp contract(off)
     if (st->done != CG_RUNNING) return;
     __shared__ __align__(16) double lds[SPMV_CAP];
@@ -869,6 +894,7 @@ bi_spmv_ts(int32_t n, int32_t g_vec, SpmvIdx ix, const double* __restrict__ val,
     if (ss <= st->thresh) {
         if (xcd_block() == 0 && threadIdx.x == 0) {
             st->rr = ss;
+            st->half_k = k;
             st->done = BI_HALF;
         }
         return;
@@ -896,7 +922,7 @@ bi_spmv_ts(int32_t n, int32_t g_vec, SpmvIdx ix, const double* __restrict__ val,
 
 // E: omega = (t, s) / (t, t); x = (x + alpha y) + omega z; r = s - omega t;
 // partials of (rh, r) -> PART_RZ and (r, r) -> PART_RR.  After a half-step
-// stop: x += alpha y only.
+// stop in this iteration's D (half_k == k): x += alpha y only.
 __global__ void __launch_bounds__(VEC_BLOCK)
 bi_update(int32_t n, int32_t k, int32_t g_spmv, double* __restrict__ x, const double* __restrict__ y,
           const double* __restrict__ z, const double* __restrict__ s, const double* __restrict__ t,
@@ -909,11 +935,9 @@ bi_update(int32_t n, int32_t k, int32_t g_spmv, double* __restrict__ x, const do
     const double a = st->alpha;
     const int32_t i0 = blockIdx.x * VEC_BLOCK + threadIdx.x, di = gridDim.x * VEC_BLOCK;
     if (d == BI_HALF) {
+        if (st->half_k != k) return;
         for (int32_t i = i0; i < n; i += di) x[i] = x[i] + a * y[i];
-        if (lead) {
-            st->iter = k + 1;
-            st->done = CG_CONVERGED;
-        }
+        if (lead) st->iter = k + 1;
         return;
     }
     const double ts = sum_partials_all<double, VEC_BLOCK>(part + PART_A, g_spmv, red);
@@ -996,8 +1020,8 @@ int bi_iterate(Bi& q, int chunk, int32_t max_iter) {
 #undef RP_LAUNCH
             hipLaunchKernelGGL(bi_half, gv, bv, 0, c.s, c.n, k, c.g_spmv, c.r, q.v, c.dinv, q.s, q.z, c.part, q.st);
 #define RP_LAUNCH(NW)                                                                                         \
-    hipLaunchKernelGGL((bi_spmv_ts<NW>), gs, bs, 0, c.s, c.n, c.g_vec, c.ix, c.val, q.z, q.t, q.s, c.part, q.st, \
-                       c.w)
+    hipLaunchKernelGGL((bi_spmv_ts<NW>), gs, bs, 0, c.s, c.n, k, c.g_vec, c.ix, c.val, q.z, q.t, q.s, c.part, \
+                       q.st, c.w)
             RP_DISPATCH_NW(c.xw_mode, RP_LAUNCH);
 #undef RP_LAUNCH
             hipLaunchKernelGGL(bi_update, gv, bv, 0, c.s, c.n, k, c.g_spmv, c.x, q.y, q.z, q.s, q.t, q.rh, c.r,
@@ -1039,7 +1063,7 @@ int solve_bicgstab(rp_plan* p, const double* b, double* x, const rp_solve_opts& 
             status = RP_OK;
             break;
         }
-        if (d == CG_CONVERGED) {
+        if (d == CG_CONVERGED || d == BI_HALF) {
             if (!fresh) {
                 RP_TRY(bi_true_residual(q));
                 fresh = true;

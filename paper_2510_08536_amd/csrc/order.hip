@@ -217,7 +217,7 @@ int solve_in_order(rp_plan* p, const double* b, double* x, const rp_solve_opts& 
     const int rc = o.method == RP_BICGSTAB ? solve_bicgstab(p, p->d_ro_b, p->d_ro_x, o, info, s, true)
                    : o.precision == RP_FP64
                        ? solve_fp64(p, p->d_ro_b, p->d_ro_x, o, info, s, true)
-                       : solve_mixed(p, p->d_ro_b, p->d_ro_x, o, info, s, o.precision == RP_MIXED, true);
+                       : solve_mixed(p, p->d_ro_b, p->d_ro_x, o, info, s, o.precision == RP_MIXED_RR, true);
     // the solvers leave an iterate in x on these outcomes; on the others they
     // stopped before touching it
     if (rc == RP_OK || rc == RP_NOT_CONVERGED || rc == RP_ERR_BREAKDOWN) {

@@ -60,7 +60,8 @@ enum : int32_t {
     CG_BREAKDOWN = 2,   // p.Ap <= 0, (r, z) <= 0 or not finite
     CG_ZERO_RHS = 4,    // ||b|| = 0
     CG_PAUSED = 5,      // residual fell below pause_thresh: FP64 update due
-    BI_HALF = 6,        // BiCGStab: ||s|| small at the half step, x += alpha y due
+    BI_HALF = 6,        // BiCGStab: ||s|| small at the half step of iteration half_k;
+                        // that iteration's last kernel adds alpha y, then the solve ends
 };
 
 template <typename S>
@@ -90,6 +91,8 @@ struct BiState {
     double rr_true; // (r, r) of the last explicit residual b - A x
     int32_t iter;   // completed iterations
     int32_t done;   // CG_* / BI_HALF
+    int32_t half_k; // iteration whose half step stopped (valid while done == BI_HALF)
+    int32_t pad;
 };
 
 // partial-sum regions of plan->d_partials (counted in elements of S)
@@ -197,6 +200,7 @@ struct rp_plan {
     int32_t xw_d[2] = {0, 0};
 
     hipStream_t last_stream = nullptr;
+    int32_t vec_grid_override = 0;     // rp_plan_set_vec_grid: solver vector-kernel blocks (0 = sized to n)
 
     // solve order (order.hip): 0 fused rows, 1 reverse Cuthill-McKee
     // renumbering for CG and the mixed solvers (built on first use)
@@ -250,12 +254,20 @@ inline int vec_grid(int64_t n) {
     if (g > VEC_GRID_MAX) g = VEC_GRID_MAX;
     return (int)g;
 }
+// rp_plan_set_vec_grid may raise the solvers' vector grid up to this many
+// blocks (far more than the chip holds at once), so that blocks of one launch
+// start after others have finished
+constexpr int VEC_GRID_LIMIT = 16384;
+// the vector grid of the plan's solver kernels
+inline int plan_vec_grid(const rp_plan* p) {
+    return p->vec_grid_override > 0 ? p->vec_grid_override : vec_grid(p->n_rows);
+}
 // partial-sum regions (in elements): two SpMV-grid ones, two vector-grid ones
-constexpr int PART_A = 0;                               // pq, or rr of b - A x
-constexpr int PART_B = SPMV_GRID_MAX;                   // bb
-constexpr int PART_RZ = 2 * SPMV_GRID_MAX;              // (r, z)
-constexpr int PART_RR = 2 * SPMV_GRID_MAX + VEC_GRID_MAX;  // (r, r)
-constexpr int PART_TOTAL = 2 * SPMV_GRID_MAX + 2 * VEC_GRID_MAX;
+constexpr int PART_A = 0;                                    // pq, or rr of b - A x
+constexpr int PART_B = SPMV_GRID_MAX;                        // bb
+constexpr int PART_RZ = 2 * SPMV_GRID_MAX;                   // (r, z)
+constexpr int PART_RR = 2 * SPMV_GRID_MAX + VEC_GRID_LIMIT;  // (r, r)
+constexpr int PART_TOTAL = 2 * SPMV_GRID_MAX + 2 * VEC_GRID_LIMIT;
 
 // plan.hip
 int plan_build(rp_plan* p, const rp_rank_desc* share);
@@ -271,8 +283,8 @@ int launch_spmv32(rp_plan* p, const float* x, float* y, hipStream_t s);
 // ordered: run on the solve-order copy (b, x in solve order)
 int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
                hipStream_t s, bool ordered = false);
-// reliable = true: FP32 PCG with FP64 residual replacement (RP_MIXED);
-// false: restarted FP32 inner PCG under FP64 refinement (RP_MIXED_IR)
+// reliable = true: FP32 PCG with FP64 residual replacement (RP_MIXED_RR);
+// false: restarted FP32 inner PCG under FP64 refinement (RP_MIXED)
 int solve_bicgstab(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
                    hipStream_t s, bool ordered = false);
 int build_transpose(rp_plan* p, hipStream_t s);

@@ -35,7 +35,7 @@ RP_ERR_HIP = -4
 RP_ERR_UNSUPPORTED = -5
 RP_ERR_BREAKDOWN = -6
 RP_ERR_VALUE = -7
-RP_FP64, RP_MIXED, RP_FP32, RP_MIXED_IR = 0, 1, 2, 3
+RP_FP64, RP_MIXED, RP_FP32, RP_MIXED_RR = 0, 1, 2, 3
 RP_CG, RP_BICGSTAB = 0, 1
 RP_KERNEL_SPMV64, RP_KERNEL_SPMV32, RP_KERNEL_SCATTER = 0, 1, 2
 
@@ -47,7 +47,8 @@ EXPORTED = ["rp_plan_create", "rp_plan_destroy", "rp_plan_sizes", "rp_plan_get_c
             "rp_plan_spmv_windows", "rp_plan_set_spmv_windows", "rp_plan_spmv_format", "rp_plan_set_spmv_format",
             "rp_update_values", "rp_update_values_slots", "rp_spmv", "rp_solve", "rp_solve_opts_default",
             "rp_value_grad", "rp_sync", "rp_last_error", "rp_plan_set_timing", "rp_plan_kernel_stats",
-            "rp_plan_set_solve_order", "rp_plan_solve_order", "rp_rcm_order"]
+            "rp_plan_set_solve_order", "rp_plan_solve_order", "rp_rcm_order", "rp_plan_device_ptrs",
+            "rp_plan_set_vec_grid"]
 
 
 class rp_rank_desc(C.Structure):
@@ -68,6 +69,15 @@ class rp_solve_opts(C.Structure):
 class rp_solve_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("outer_iters", C.c_int32),
                 ("restarts", C.c_int32), ("rel_res", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class rp_device_ptrs(C.Structure):
+    _fields_ = [("row_ptr", C.c_void_p), ("col", C.c_void_p), ("perm", C.c_void_p), ("nl_row_ptr", C.c_void_p),
+                ("nl_col", C.c_void_p), ("val64", C.c_void_p), ("val32", C.c_void_p), ("dinv64", C.c_void_p),
+                ("dinv32", C.c_void_p), ("recv", C.c_void_p)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -111,6 +121,8 @@ _sig = {
     "rp_plan_set_solve_order": (C.c_int, [_P, C.c_int32]),
     "rp_plan_solve_order": (C.c_int, [_P, _i32p, _P]),
     "rp_rcm_order": (C.c_int, [C.c_int32, _P, _P, _P]),
+    "rp_plan_device_ptrs": (C.c_int, [_P, C.POINTER(rp_device_ptrs)]),
+    "rp_plan_set_vec_grid": (C.c_int, [_P, C.c_int32]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -168,16 +180,22 @@ def rcm_order(row_ptr, col) -> np.ndarray:
     return perm[:n]
 
 
-def default_opts(**kw) -> rp_solve_opts:
-    o = rp_solve_opts()
-    rp_solve_opts_default(C.byref(o))
+def _set_opts(o: rp_solve_opts, **kw) -> rp_solve_opts:
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
-            v = {"fp64": RP_FP64, "mixed": RP_MIXED, "mixed_ir": RP_MIXED_IR}[v]
+            v = {"fp64": RP_FP64, "mixed": RP_MIXED, "mixed_rr": RP_MIXED_RR}[v]
         if k == "method" and isinstance(v, str):
             v = {"cg": RP_CG, "bicgstab": RP_BICGSTAB}[v]
         setattr(o, k, v)
     return o
+
+
+def default_opts(**kw) -> rp_solve_opts:
+    """The library's default options with the named fields changed
+    (precision "fp64" / "mixed" / "mixed_rr", method "cg" / "bicgstab")."""
+    o = rp_solve_opts()
+    rp_solve_opts_default(C.byref(o))
+    return _set_opts(o, **kw)
 
 
 class Plan:
@@ -287,6 +305,16 @@ class Plan:
         return dict(row_ptr=row_ptr, col=col[:self.nnz], perm=perm[:self.n_slots], nl_row_ptr=nl_row_ptr,
                     nl_col=nl_col[:self.nnz_nonlocal])
 
+    def device_ptrs(self) -> dict:
+        """Device addresses of the pattern and value arrays (rp_plan_device_ptrs)."""
+        d = rp_device_ptrs()
+        _check(rp_plan_device_ptrs(self._h, C.byref(d)), "rp_plan_device_ptrs")
+        return d.as_dict()
+
+    def set_vec_grid(self, blocks: int):
+        """Fix the solvers' elementwise-kernel grid (0 = default sizing)."""
+        _check(rp_plan_set_vec_grid(self._h, int(blocks)), "rp_plan_set_vec_grid")
+
     def get_values(self):
         v64 = np.zeros(max(self.n_slots, 1), np.float64)
         v32 = np.zeros(max(self.n_slots, 1), np.float32)
@@ -346,9 +374,15 @@ class Plan:
         return y
 
     def solve(self, b, x=None, opts=None, stream=None, check=True, **kw):
-        """Solve A x = b (b, x float64 CUDA tensors).  Returns (x, info dict)."""
+        """Solve A x = b (b, x float64 CUDA tensors).  Returns (x, info dict).
+        opts is read, never changed; keyword arguments set fields of a copy."""
         torch = _torch()
-        o = opts if opts is not None else default_opts(**kw)
+        if opts is None:
+            o = default_opts(**kw)
+        else:
+            o = rp_solve_opts()
+            C.memmove(C.byref(o), C.byref(opts), C.sizeof(rp_solve_opts))
+            _set_opts(o, **kw)
         if x is None:
             x = torch.zeros_like(b)
             o.x0_zero = 1

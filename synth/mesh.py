@@ -105,6 +105,40 @@ def structured_mesh(nx: int, ny: int, nz: int, dz=None, walls=(True, True, True)
                 n_interior)
 
 
+def box27_mesh(nx: int, ny: int, nz: int) -> Mesh:
+    """Unit cells coupled to all 26 neighbours (faces, edges and corners of
+    the cell), so every interior row holds 27 entries: rows with far more
+    couplings than a 7-point stencil, as polyhedral finite-volume cells have.
+    Interior "faces" are the neighbour pairs, listed per offset (13 offsets
+    with a positive first non-zero component in z, y, x order) in the natural
+    order of the minus-side cell; geometric weight 1 / |offset|^2.  Walls as
+    structured_mesh on all six sides."""
+    idx = np.arange(nx * ny * nz, dtype=np.int64).reshape(nz, ny, nx)
+    offs = [(dz_, dy_, dx_) for dz_ in (-1, 0, 1) for dy_ in (-1, 0, 1) for dx_ in (-1, 0, 1)
+            if (dz_, dy_, dx_) > (0, 0, 0)]
+    a_parts, b_parts, g_parts = [], [], []
+    for dz_, dy_, dx_ in offs:
+        zs = slice(max(0, -dz_), nz - max(0, dz_))
+        ys = slice(max(0, -dy_), ny - max(0, dy_))
+        xs = slice(max(0, -dx_), nx - max(0, dx_))
+        a = idx[zs, ys, xs].ravel()
+        a_parts.append(a)
+        b_parts.append(a + dx_ + nx * (dy_ + ny * dz_))
+        g_parts.append(np.full(a.shape[0], 1.0 / (dx_ * dx_ + dy_ * dy_ + dz_ * dz_)))
+    n_interior = int(sum(p.shape[0] for p in a_parts))
+    for sl in (idx[:, :, 0], idx[:, :, -1], idx[:, 0, :], idx[:, -1, :], idx[0], idx[-1]):
+        c = sl.ravel()
+        a_parts.append(c)
+        g_parts.append(np.ones(c.shape[0]))
+    n_wall = int(sum(p.shape[0] for p in a_parts)) - n_interior
+    b_parts.append(np.full(n_wall, -1, dtype=np.int64))
+    return Mesh(nx, ny, nz, np.ones(nz), (True, True, True),
+                np.ascontiguousarray(np.concatenate(a_parts)),
+                np.ascontiguousarray(np.concatenate(b_parts)),
+                np.ascontiguousarray(np.concatenate(g_parts)),
+                n_interior)
+
+
 # ----------------------------------------------------------------------------
 # decompositions: natural cell id -> rank
 # ----------------------------------------------------------------------------

@@ -18,7 +18,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .mesh import (Mesh, Partition, LduValues, structured_mesh, stretched_dz,
+from .mesh import (Mesh, Partition, LduValues, structured_mesh, stretched_dz, box27_mesh,
                    decompose_blocks, decompose_rcb, partition, ldu_values, stream_fluxes, momentum_ldu)
 
 
@@ -34,6 +34,7 @@ class Recipe:
     scramble: bool = False
     walls: tuple = (True, True, True)
     note: str = ""
+    stencil: int = 7               # 7: face neighbours; 27: all 26 neighbours (box27_mesh)
 
 
 RECIPES = {
@@ -124,7 +125,11 @@ def build(recipe: Recipe | str, **overrides) -> Workload:
     seqs = np.random.SeedSequence(recipe.seed).spawn(5 + max(recipe.timesteps, 1))
     s_coef, s_rhs, s_tgt, s_perm, s_rcb = seqs[:5]
     dz = stretched_dz(nz, recipe.stretch) if recipe.stretch else None
-    mesh = structured_mesh(nx, ny, nz, dz=dz, walls=recipe.walls)
+    if recipe.stencil == 27:
+        assert dz is None and recipe.walls == (True, True, True)
+        mesh = box27_mesh(nx, ny, nz)
+    else:
+        mesh = structured_mesh(nx, ny, nz, dz=dz, walls=recipe.walls)
     n = mesh.n_cells
 
     gid = None

@@ -41,3 +41,22 @@ def random_ldu_values(w, rng, symmetric=False):
                         lower=up if symmetric else rng.uniform(-1, 1, nf),
                         iface=rng.uniform(-1, 1, ni)))
     return out
+
+
+def golden_reference(name):
+    """The oracle's reference solution of a full-size pressure system
+    (tests/golden/ref_<name>.json, written by make_full_size_refs.py): the
+    record, the sampled rows and x_ref on them."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"ref_{name}.json")
+    with open(path) as f:
+        d = json.load(f)
+    rows = np.asarray(d["rows"], dtype=np.int64)
+    x_ref = np.asarray([float(v) for v in d["x_ref"]], dtype=np.float64)
+    return d, rows, x_ref
+
+
+def sampled_rel_err(x, rows, x_ref):
+    """||x - x_ref|| / ||x_ref|| over the sampled rows."""
+    return float(np.linalg.norm(np.asarray(x)[rows] - x_ref) / np.linalg.norm(x_ref))

@@ -2,12 +2,15 @@
 benchmark times.
 
 Pattern, permutation and values are compared with the oracle in full (bit
-for bit).  Solves are checked by the true relative residual the oracle's own
-SpMV computes for the GPU answer (<= 1e-8) and, where the oracle's serial
-solve fits in the test (32^3, 128^3, 96^3), by the error against the oracle's
-solution.  For the 256^3 and 160^3 systems (condition numbers far above the
-others) the FP64 and mixed answers are compared with each other and their
-difference is bounded by what a 1e-8 residual allows.
+for bit), at every timestep of the 128^3 and 160^3 sequences.  Solves are
+checked by the true relative residual the oracle's own SpMV computes for the
+GPU answer (<= 1e-8) and by the error against the oracle's solution: where
+the oracle's serial solve fits in the test (32^3, 128^3, 96^3) against its
+1e-8 solution (<= 1e-6); for the 256^3 and 160^3 systems, whose condition
+numbers put a 1e-8 residual far from a 1e-6 error, against the oracle solved
+to 1e-12 on a seeded sample of 8,192 rows (tests/golden/ref_*.json).  There
+each GPU answer's error is printed and held to at most ten times the error
+of the oracle's own 1e-8 solution against the same reference.
 """
 import gc
 
@@ -16,7 +19,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import share_ranks, share_values
+from helpers import share_ranks, share_values, golden_reference, sampled_rel_err
 from gpu_util import torch_mod, dev_tensor, make_plan, update, assert_bits_equal
 
 pytestmark = pytest.mark.gpu
@@ -54,9 +57,11 @@ def test_c1_full():
     plan.close()
 
 
-@pytest.mark.timeout(600)
+@pytest.mark.timeout(900)
 def test_c2_timesteps():
-    """128^3, 32 ranks: per timestep update (bit-exact) + FP64 PCG."""
+    """128^3, 32 ranks, all 20 timesteps: update (bit-exact) + FP64 PCG
+    (oracle residual each step, error against the oracle at the first and
+    last step)."""
     w = synth.build("c2")
     m = oracle.merge(w.part.n_cells, 0, w.n_ranks, share_ranks(w))
     plan = make_plan(w)
@@ -65,8 +70,9 @@ def test_c2_timesteps():
         assert np.array_equal(g[k], getattr(m, k)), k
     b = w.rhs()
     bt = dev_tensor(b)
-    x = None
-    for t in range(3):
+    T = w.recipe.timesteps
+    assert T == 20
+    for t in range(T):
         vals = share_values(w, t)
         want = oracle.update(m, oracle.receive_buffer(vals))
         update(plan, vals)
@@ -75,32 +81,43 @@ def test_c2_timesteps():
             assert_bits_equal(gv, wv, f"t={t} {what}")
         x, info = plan.solve(bt, tol=1e-8)
         xh = x.cpu().numpy()
-        assert info["status"] == 0 and oracle.true_relres(m, want[0], b, xh) <= 1e-8
-        if t == 0:
-            x_or, st, it_or, *_ = oracle.pcg(m, want[0], b, tol=1e-8)
-            assert st == 0
-            assert np.linalg.norm(xh - x_or) <= 1e-6 * np.linalg.norm(x_or)
+        rr = oracle.true_relres(m, want[0], b, xh)
+        assert info["status"] == 0 and info["restarts"] == 0 and rr <= 1e-8, (t, info, rr)
+        if t in (0, T - 1):
+            x_or, st, it_or, rs_or, _ = oracle.pcg(m, want[0], b, tol=1e-8)
+            assert st == 0 and rs_or == 0
+            err = np.linalg.norm(xh - x_or) / np.linalg.norm(x_or)
+            print(f"c2 t={t}: {info['iters']} it (oracle {it_or}), rel.res {rr:.2e}, err {err:.2e}")
+            assert err <= 1e-6
             assert abs(info["iters"] - it_or) <= max(3, 0.02 * it_or), (info["iters"], it_or)
     plan.close()
 
 
-def _fp64_vs_mixed(plan, m, val64, b):
+def _against_reference(name, plan, m, val64, b, runs):
+    """Solve with each (label, kwargs) of runs; check the oracle residual,
+    restarts and the sampled error against the oracle's 1e-12 solution."""
+    ref, rows, x_ref = golden_reference(name)
+    own = ref["oracle_1e-8"]["rel_err_vs_ref_sampled"]
+    bound = 10.0 * own
+    print(f"{name}: oracle 1e-8 solution: {ref['oracle_1e-8']['iters']} it, error vs 1e-12 reference "
+          f"{ref['oracle_1e-8']['rel_err_vs_ref']:.2e} (sampled {own:.2e}); bound {bound:.2e}")
     bt = dev_tensor(b)
-    x64, i64 = plan.solve(bt, tol=1e-8, precision="fp64")
-    xm, im = plan.solve(bt, tol=1e-8, precision="mixed")
-    xi, ii = plan.solve(bt, tol=1e-8, precision="mixed_ir")
-    assert ii["status"] == 0 and oracle.true_relres(m, val64, b, xi.cpu().numpy()) <= 1e-8, ii
-    print(f"  mixed_ir: {ii['iters']} inner / {ii['outer_iters']} outer")
-    x64h, xmh = x64.cpu().numpy(), xm.cpu().numpy()
-    r64 = oracle.true_relres(m, val64, b, x64h)
-    rm = oracle.true_relres(m, val64, b, xmh)
-    assert i64["status"] == 0 and im["status"] == 0 and r64 <= 1e-8 and rm <= 1e-8, (i64, im, r64, rm)
-    return x64h, xmh, i64, im
+    for label, kw in runs:
+        x, info = plan.solve(bt, tol=1e-8, **kw)
+        xh = x.cpu().numpy()
+        rr = oracle.true_relres(m, val64, b, xh)
+        err = sampled_rel_err(xh, rows, x_ref)
+        print(f"  {label}: {info['iters']} it / {info['outer_iters']} outer, restarts {info['restarts']}, "
+              f"rel.res {rr:.2e}, error vs reference {err:.2e}")
+        assert info["status"] == 0 and rr <= 1e-8, (label, info, rr)
+        assert info["restarts"] == 0, (label, info)
+        assert err <= bound, (label, err, bound)
 
 
 @pytest.mark.timeout(900)
 def test_c3_fp64_and_mixed():
-    """256^3, 64 ranks, kappa in [1e-3, 1]."""
+    """256^3, 64 ranks, kappa in [1e-3, 1]: FP64, mixed refinement and
+    residual replacement against the oracle's 1e-12 solution."""
     w = synth.build("c3")
     m, vals, want = _system(w)
     plan = make_plan(w)
@@ -111,12 +128,9 @@ def test_c3_fp64_and_mixed():
     want = None
     gc.collect()
     b = w.rhs()
-    x64, xm, i64, im = _fp64_vs_mixed(plan, m, val64, b)
-    # both meet 1e-8; their difference is what the residual bound allows
-    diff = np.linalg.norm(x64 - xm) / np.linalg.norm(x64)
-    print(f"c3: fp64 {i64['iters']} it, mixed {im['iters']} inner / {im['outer_iters']} outer, "
-          f"rel diff {diff:.2e}")
-    assert diff <= 1e-2
+    _against_reference("c3", plan, m, val64, b,
+                       [("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed")),
+                        ("mixed_rr", dict(precision="mixed_rr"))])
     # the same plan refreshed with non-symmetric momentum-type values:
     # update bit-exact, BiCGStab to a true residual of 1e-8
     del val64
@@ -128,8 +142,8 @@ def test_c3_fp64_and_mixed():
     _check_plan_and_update(plan, m, want)
     xb, ib = plan.solve(dev_tensor(b), tol=1e-8, method="bicgstab")
     rr = oracle.true_relres(m, want[0], b, xb.cpu().numpy())
-    print(f"c3 momentum: bicgstab {ib['iters']} it, true rel.res {rr:.2e}")
-    assert ib["status"] == 0 and rr <= 1e-8
+    print(f"c3 momentum: bicgstab {ib['iters']} it, restarts {ib['restarts']}, true rel.res {rr:.2e}")
+    assert ib["status"] == 0 and ib["restarts"] == 0 and rr <= 1e-8
     plan.close()
 
 
@@ -178,8 +192,8 @@ def test_c4_adjoint_full():
 
 @pytest.mark.timeout(900)
 def test_c5_scrambled_mixed_and_adjoint():
-    """160^3 stretched, scrambled ids, 48 RCB ranks: two timesteps of
-    update + mixed PCG + adjoint."""
+    """160^3 stretched, scrambled ids, 48 RCB ranks: all 10 timesteps of
+    update (bit-exact) + mixed PCG + adjoint (lambda solve + slot gradient)."""
     w = synth.build("c5")
     m = oracle.merge(w.part.n_cells, 0, w.n_ranks, share_ranks(w))
     plan = make_plan(w)
@@ -187,7 +201,9 @@ def test_c5_scrambled_mixed_and_adjoint():
     for k in ("row_ptr", "col", "perm"):
         assert np.array_equal(g[k], getattr(m, k)), k
     b, xt = w.rhs(), w.target()
-    for t in range(2):
+    T = w.recipe.timesteps
+    assert T == 10
+    for t in range(T):
         vals = share_values(w, t)
         want = oracle.update(m, oracle.receive_buffer(vals))
         update(plan, vals)
@@ -196,26 +212,34 @@ def test_c5_scrambled_mixed_and_adjoint():
             assert_bits_equal(gv, wv, f"t={t} {what}")
         x, info = plan.solve(dev_tensor(b), tol=1e-8, precision="mixed")
         xh = x.cpu().numpy()
-        assert info["status"] == 0 and oracle.true_relres(m, want[0], b, xh) <= 1e-8, info
+        rr = oracle.true_relres(m, want[0], b, xh)
+        assert info["status"] == 0 and rr <= 1e-8, (t, info, rr)
         lam, info2 = plan.solve(dev_tensor(xh - xt), tol=1e-8, precision="mixed")
-        assert oracle.true_relres(m, want[0], xh - xt, lam.cpu().numpy()) <= 1e-8
+        lamh = lam.cpu().numpy()
+        rl = oracle.true_relres(m, want[0], xh - xt, lamh)
+        assert info2["status"] == 0 and rl <= 1e-8, (t, info2, rl)
         gs = plan.value_grad(lam, x).cpu().numpy()
-        assert_bits_equal(gs, oracle.value_grad(m, lam.cpu().numpy(), xh), "slot gradient")
+        assert_bits_equal(gs, oracle.value_grad(m, lamh, xh), f"t={t} slot gradient")
+        print(f"c5 t={t}: mixed {info['iters']} it / {info['outer_iters']} outer, rel.res {rr:.2e}; "
+              f"adjoint {info2['iters']} it, rel.res {rl:.2e}")
     plan.close()
 
 
-def test_c5_fp64_and_mixed_in_rcm_order():
-    """160^3 scrambled: FP64 and mixed PCG on the reverse Cuthill-McKee solve
-    order reach the 1e-8 true residual of the fused system."""
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("order", ["fused", "rcm"])
+def test_c5_solves_against_reference(order):
+    """160^3 scrambled, timestep 0: FP64, mixed refinement and residual
+    replacement, in fused and in reverse Cuthill-McKee solve order, against
+    the oracle's 1e-12 solution."""
     w = synth.build("c5")
     m = oracle.merge(w.part.n_cells, 0, w.n_ranks, share_ranks(w))
     plan = make_plan(w)
-    plan.set_solve_order("rcm")
+    if order == "rcm":
+        plan.set_solve_order("rcm")
     vals = share_values(w, 0)
     want = oracle.update(m, oracle.receive_buffer(vals))
     update(plan, vals)
-    b = w.rhs()
-    for precision in ("fp64", "mixed"):
-        x, info = plan.solve(dev_tensor(b), tol=1e-8, precision=precision)
-        assert info["status"] == 0 and oracle.true_relres(m, want[0], b, x.cpu().numpy()) <= 1e-8, (precision, info)
+    _against_reference("c5", plan, m, want[0], w.rhs(),
+                       [("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed")),
+                        ("mixed_rr", dict(precision="mixed_rr"))])
     plan.close()

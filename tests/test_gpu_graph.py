@@ -35,7 +35,7 @@ def _solve(plan, b, x, **kw):
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
-@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_ir"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_rr"])
 def test_graph_replays_match_eager(name, precision):
     torch = torch_mod()
     w = CASES[name]()

@@ -1,0 +1,91 @@
+"""Solves with far more elementwise-kernel blocks than the chip holds at once.
+
+Blocks of one launch may start after block 0 has finished, so a kernel must
+not gate its work on device state that its own block 0 writes in the same
+launch.  rp_plan_set_vec_grid fixes the solvers' vector grid at 16384 blocks;
+on the 96^3 system (884,736 rows) every block up to 3455 owns rows, so most of
+them start after the first blocks are done.  FP64 CG, both mixed forms and
+BiCGStab must still match the oracle with no true-residual restart.
+Tolerances as in test_gpu_solve: true relative residual <= 1e-8 by the
+oracle's SpMV and solution error <= 1e-6 against the oracle's x."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import share_values, share_ranks
+from gpu_util import dev_tensor, make_plan, update
+
+pytestmark = pytest.mark.gpu
+
+LATE_GRID = 16384
+
+
+@pytest.fixture(scope="module")
+def c4():
+    w = synth.build("c4")
+    m = oracle.merge(w.part.n_cells, 0, w.n_ranks, share_ranks(w))
+    return w, m
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_rr"])
+def test_cg_with_late_blocks(c4, precision):
+    w, m = c4
+    vals = share_values(w)
+    val64, *_ = oracle.update(m, oracle.receive_buffer(vals))
+    plan = make_plan(w)
+    update(plan, vals)
+    b = w.rhs()
+    x_or, st, it_or, rs_or, _ = oracle.pcg(m, val64, b, tol=1e-8)
+    assert st == 0 and rs_or == 0
+    ref, ref_info = plan.solve(dev_tensor(b), tol=1e-8, precision=precision)
+    plan.set_vec_grid(LATE_GRID)
+    for graph in (0, 1):
+        x, info = plan.solve(dev_tensor(b), tol=1e-8, precision=precision, graph=graph)
+        xh = x.cpu().numpy()
+        rr = oracle.true_relres(m, val64, b, xh)
+        err = np.linalg.norm(xh - x_or) / np.linalg.norm(x_or)
+        print(f"{precision} graph={graph}: {info['iters']} it (oracle {it_or}, default grid "
+              f"{ref_info['iters']}), restarts {info['restarts']}, rel.res {rr:.2e}, err {err:.2e}")
+        assert info["status"] == 0 and info["restarts"] == 0, info
+        assert rr <= 1e-8 and err <= 1e-6, (rr, err)
+        if precision == "fp64":
+            assert abs(info["iters"] - it_or) <= max(3, int(0.02 * it_or)), (info["iters"], it_or)
+    plan.set_vec_grid(0)
+    plan.close()
+
+
+@pytest.mark.timeout(300)
+def test_bicgstab_with_late_blocks(c4):
+    w, m = c4
+    mv = share_values(w, values=w.momentum_values())
+    val64, *_ = oracle.update(m, oracle.receive_buffer(mv))
+    plan = make_plan(w)
+    update(plan, mv, lower=True)
+    b = w.rhs()
+    x_or, st, it_or, rs_or, _ = oracle.bicgstab(m, val64, b, tol=1e-8)
+    assert st == 0 and rs_or == 0
+    plan.set_vec_grid(LATE_GRID)
+    x, info = plan.solve(dev_tensor(b), tol=1e-8, method="bicgstab")
+    xh = x.cpu().numpy()
+    rr = oracle.true_relres(m, val64, b, xh)
+    err = np.linalg.norm(xh - x_or) / np.linalg.norm(x_or)
+    print(f"bicgstab: {info['iters']} it (oracle {it_or}), restarts {info['restarts']}, rel.res {rr:.2e}, "
+          f"err {err:.2e}")
+    assert info["status"] == 0 and info["restarts"] == 0, info
+    assert rr <= 1e-8 and err <= 1e-6
+    plan.close()
+
+
+def test_vec_grid_bounds():
+    from paper_2510_08536_amd import RpError, RP_ERR_ARG
+    w = synth.small((6, 5, 4), ("blocks", 2, 1, 1), seed=3)
+    plan = make_plan(w)
+    for bad in (-1, LATE_GRID + 1):
+        with pytest.raises(RpError) as e:
+            plan.set_vec_grid(bad)
+        assert e.value.code == RP_ERR_ARG
+    plan.set_vec_grid(LATE_GRID)
+    plan.set_vec_grid(0)
+    plan.close()

@@ -40,17 +40,18 @@ def _iters_close(a, b):
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
-@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_ir"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_rr"])
 def test_solve_matches_oracle(name, precision):
     w, m, val64, plan = _setup(name)
     b = w.rhs()
-    x_or, st, it_or, _, rr_or = oracle.pcg(m, val64, b, tol=1e-8)
-    assert st == 0
+    x_or, st, it_or, rs_or, rr_or = oracle.pcg(m, val64, b, tol=1e-8)
+    assert st == 0 and rs_or == 0
     x, info = plan.solve(dev_tensor(b), tol=1e-8, precision=precision)
     xh = x.cpu().numpy()
     rr = oracle.true_relres(m, val64, b, xh)
     err = np.linalg.norm(xh - x_or) / np.linalg.norm(x_or)
     assert info["status"] == 0 and rr <= 1e-8, (info, rr)
+    assert info["restarts"] == 0, info
     assert abs(info["rel_res"] - rr) <= 1e-3 * rr + 1e-15
     assert err <= 1e-6, err
     if precision == "fp64":
@@ -86,7 +87,7 @@ def test_tridiagonal_closed_form():
     idx = np.arange(1, N + 1)
     Ainv = np.minimum.outer(idx, idx) * (N + 1 - np.maximum.outer(idx, idx)) / (N + 1)
     b = np.random.default_rng(6).uniform(-1, 1, N)
-    for prec in ("fp64", "mixed", "mixed_ir"):
+    for prec in ("fp64", "mixed", "mixed_rr"):
         x, info = plan.solve(dev_tensor(b), tol=1e-12 if prec == "fp64" else 1e-10, precision=prec)
         ref = Ainv @ b
         assert np.max(np.abs(x.cpu().numpy() - ref)) <= 1e-8 * np.max(np.abs(ref)), prec
@@ -153,7 +154,7 @@ def test_zero_rhs_and_warm_start():
     x_cold, info_cold = plan.solve(dev_tensor(b), tol=1e-8)
     x_w, info_w = plan.solve(dev_tensor(b), x=dev_tensor(x_or * (1 + 1e-4)), tol=1e-8)
     assert info_w["iters"] < info_cold["iters"]
-    for prec in ("fp64", "mixed", "mixed_ir"):
+    for prec in ("fp64", "mixed", "mixed_rr"):
         x, info = plan.solve(torch.zeros(m.n_rows, dtype=torch.float64, device="cuda:0"), precision=prec)
         assert info["status"] == 0 and (x.cpu().numpy() == 0).all()
     plan.close()

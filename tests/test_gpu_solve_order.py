@@ -44,7 +44,7 @@ def _check_against_oracle(m, val64, b, x, info, it_or=None):
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
-@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_ir"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_rr"])
 def test_solve_in_rcm_order_matches_oracle(name, precision):
     w, m, val64, plan = _setup(name)
     plan.set_solve_order("rcm")          # before the first update
