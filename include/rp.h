@@ -95,7 +95,8 @@ typedef struct rp_rank_desc {
 typedef struct rp_solve_opts {
     double tol;              /* stop when ||b - A x||_2 <= tol ||b||_2 (default 1e-8) */
     double inner_tol;        /* RP_MIXED: each inner FP32 PCG stops at this relative
-                                residual (default 1e-4) */
+                                residual, or earlier once its residual is below
+                                tol ||b|| / 2 (default 1e-4) */
     double update_delta;     /* RP_MIXED_RR: the FP64 update is due once the FP32 residual has
                                 fallen by this factor since the last one (default 0.1) */
     int32_t max_iter;        /* FP64: CG iterations; mixed: total FP32 iterations */
@@ -272,7 +273,8 @@ int rp_spmv(rp_plan* plan, int32_t precision, const void* x, void* y, void* stre
  * is iterative refinement: the FP64 residual r = b - A x is rounded to FP32,
  * an FP32 Jacobi-PCG (FP32 matrix, preconditioner, vectors and dot products)
  * solves A d = r from d = 0 until its residual is below inner_tol times its
- * start, x += d in FP64, and this repeats until the FP64 residual meets tol.
+ * start (or below tol ||b|| / 2, the outer target, if that is reached
+ * first), x += d in FP64, and this repeats until the FP64 residual meets tol.
  * RP_MIXED_RR runs one FP32 PCG throughout and, whenever its residual has
  * fallen by update_delta, folds its correction into the FP64 solution and
  * replaces its residual by the FP64 residual b - A x, keeping the search

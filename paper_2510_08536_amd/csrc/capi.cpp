@@ -78,7 +78,7 @@ void free_plan(rp_plan* p) {
                    p->d_flags, p->d_goi_k, p->d_goi_off, p->d_goi_mask, p->d_bi_st, p->d_bi_work,
                    p->d_valT, p->d_tflag, p->d_ro_perm, p->d_ro_row_ptr, p->d_ro_col, p->d_ro_sig,
                    p->d_ro_val64, p->d_ro_val32, p->d_ro_dinv64, p->d_ro_dinv32, p->d_ro_b, p->d_ro_x,
-                   p->d_ro_valT};
+                   p->d_ro_valT, (void*)p->d_src};
     for (void* q : dev)
         if (q) (void)hipFree(q);
     if (p->h_st64) (void)hipHostFree(p->h_st64);
@@ -133,6 +133,7 @@ int alloc_values(rp_plan* p) {
     RP_HIP_TRY(hipMemset(p->d_bi_st, 0, sizeof(BiState)));
     RP_HIP_TRY(hipHostMalloc((void**)&p->h_bi_st, sizeof(BiState), hipHostMallocDefault));
     RP_HIP_TRY(hipHostMalloc((void**)&p->h_flags, 2 * sizeof(uint32_t), hipHostMallocDefault));
+    RP_HIP_TRY(hipMalloc((void**)&p->d_src, sizeof(const double*) * 4 * (size_t)std::max(p->alpha, 1)));
     return RP_OK;
 }
 
@@ -238,9 +239,13 @@ int update(rp_plan* p, const double* const* diag, const double* const* upper, co
         p->h_src[4 * i + 2] = lower ? lower[i] : upper[i];
         p->h_src[4 * i + 3] = iface[i];
     }
-    RP_HIP_TRY(hipMemsetAsync(p->d_flags, 0, 2 * sizeof(uint32_t), s));
+    RP_TRY(launch_clear_flags(p->d_flags, s));
     if (all_device) {
-        RP_TRY(launch_stage_table(p, lower != nullptr, s));
+        // the receive buffer stays virtual: the reorder reads every slot from
+        // its rank's array through the pointer table
+        RP_HIP_TRY(hipMemcpyAsync(p->d_src, p->h_src.data(), sizeof(const double*) * 4 * (size_t)p->alpha,
+                                  hipMemcpyHostToDevice, s));
+        RP_TRY(launch_update_gather(p, p->d_src, lower != nullptr, p->d_flags, s));
     } else {
         // host-buffer path: one copy per rank array into the receive buffer at U's offsets
         for (int32_t i = 0; i < p->alpha; ++i) {
@@ -252,9 +257,9 @@ int update(rp_plan* p, const double* const* diag, const double* const* upper, co
                                               hipMemcpyDefault, s));
             if (ni) RP_HIP_TRY(hipMemcpyAsync(dst + nc + 2 * nf, iface[i], ni * 8, hipMemcpyDefault, s));
         }
+        RP_TRY(launch_symmetry_check(p, p->d_recv, lower != nullptr, s));
+        RP_TRY(launch_update(p, p->d_recv, s));
     }
-    RP_TRY(launch_symmetry_check(p, p->d_recv, lower != nullptr, s));
-    RP_TRY(launch_update(p, p->d_recv, s));
     p->has_values = true;
     p->values_version += 1;
     p->last_stream = s;
@@ -414,7 +419,7 @@ int rp_update_values_slots(rp_plan* p, const double* slots, void* stream) {
     RP_CHECK(slots != nullptr || p->n_slots == 0, RP_ERR_ARG, "slots is NULL");
     RP_TRY(activate(p));
     hipStream_t s = as_stream(stream);
-    RP_HIP_TRY(hipMemsetAsync(p->d_flags, 0, 2 * sizeof(uint32_t), s));
+    RP_TRY(launch_clear_flags(p->d_flags, s));
     RP_TRY(launch_symmetry_check(p, slots, true, s));
     RP_TRY(launch_update(p, slots, s));
     p->has_values = true;

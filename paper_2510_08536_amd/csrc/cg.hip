@@ -660,12 +660,19 @@ int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, 
 
     // FP32 PCG from d = 0 on the current r32 (the start clears x32).
     // reliable: never stops on its own; pauses after each update_delta
-    // reduction of its residual.  Otherwise: stops at inner_tol.
-    const float tol2_in = reliable ? 0.0f : (float)(o.inner_tol * o.inner_tol);
+    // reduction of its residual.  Otherwise: stops once its residual is below
+    // inner_tol times its start, or below half the outer target tol ||b||
+    // (whichever comes first): a last refinement step need not go further
+    // than the solve asks for.
     const float pause2 = reliable ? (float)(o.update_delta * o.update_delta) : 0.0f;
     bool start_inner = true;
     while (status != RP_OK) {
         if (start_inner) {
+            float tol2_in = 0.0f;
+            if (!reliable) {
+                const double floor2 = 0.25 * thresh / rr;   // (tol ||b|| / 2)^2 relative to ||r||^2
+                tol2_in = (float)std::min(0.25, std::max(o.inner_tol * o.inner_tol, floor2));
+            }
             RP_TRY((launch_residual<float, false>(in, true, nullptr)));
             RP_TRY(launch_start(in, total_inner, tol2_in, pause2, o.max_iter));
             RP_TRY(read_state(in));

@@ -166,7 +166,8 @@ struct rp_plan {
     int64_t valT_version = -1;       // values_version d_valT was built from
     uint32_t* d_tflag = nullptr;     // set when an entry has no transposed partner
 
-    // staging table for device-resident per-rank values: 4*alpha pointers
+    // pointer table for device-resident per-rank values: 4*alpha pointers
+    // (diag, upper, lower or upper, interface of each share rank)
     const double** d_src = nullptr;
     std::vector<const double*> h_src;
 
@@ -275,7 +276,12 @@ int plan_build(rp_plan* p, const rp_rank_desc* share);
 // src: the receive buffer in slot order (the plan's own, or the caller's)
 int launch_update(rp_plan* p, const double* src, hipStream_t s);
 int launch_symmetry_check(rp_plan* p, const double* src, bool lower_given, hipStream_t s);
-int launch_stage_table(rp_plan* p, bool lower_given, hipStream_t s);
+// device-resident per-rank arrays: symmetry check and reorder by P straight
+// from table[4 * alpha] (diag, upper, lower or upper, interface per rank, a
+// device array); error bits go to flags[2]
+int launch_update_gather(rp_plan* p, const double* const* table, bool lower_given, uint32_t* flags,
+                         hipStream_t s);
+int launch_clear_flags(uint32_t* flags, hipStream_t s);
 // spmv.hip
 int launch_spmv64(rp_plan* p, const double* x, double* y, hipStream_t s);
 int launch_spmv32(rp_plan* p, const float* x, float* y, hipStream_t s);

@@ -7,6 +7,11 @@
 // same pass writes the FP32 copy (round to nearest even) and flags values
 // that are not finite; a second grid part computes the Jacobi inverse
 // diagonal as one IEEE division per row.
+//
+// Where the buffer is real (values that came from host memory, or a buffer
+// the caller filled) the kernels read it; for per-rank arrays in device
+// memory it stays virtual, and the same gather reads each slot straight
+// from its rank's array through a table of 4 pointers per rank.
 #include <algorithm>
 #include <cmath>
 
@@ -23,34 +28,6 @@ __device__ __forceinline__ int32_t find_block(const int32_t* tab, int32_t n, int
         if (tab[m] <= v) a = m; else b = m;
     }
     return a;
-}
-
-constexpr int STAGE_RANKS = 60;  // rank pointers per staging launch (kernel-argument budget)
-
-struct StageArgs {
-    const double* src[STAGE_RANKS][4];   // diag, upper, lower (or upper), iface
-    int32_t s0;                          // first share rank of this launch
-    int32_t ns;                          // ranks in this launch
-};
-
-// copy ranks s0..s0+ns-1 from their own arrays into the receive buffer
-__global__ void stage_kernel(StageArgs a, const int32_t* slot_off, const int32_t* row0, const int32_t* nf,
-                             double* recv) {
-    const int32_t k0 = slot_off[a.s0];
-    const int32_t k1 = slot_off[a.s0 + a.ns];
-    for (int32_t k = k0 + blockIdx.x * blockDim.x + threadIdx.x; k < k1; k += gridDim.x * blockDim.x) {
-        const int32_t s = a.s0 + find_block(slot_off + a.s0, a.ns, k);
-        const int32_t loc = k - slot_off[s];
-        const int32_t nc = row0[s + 1] - row0[s];
-        const int32_t f = nf[s];
-        const int ls = s - a.s0;
-        double v;
-        if (loc < nc) v = a.src[ls][0][loc];
-        else if (loc < nc + f) v = a.src[ls][1][loc - nc];
-        else if (loc < nc + 2 * f) v = a.src[ls][2][loc - nc - f];
-        else v = a.src[ls][3][loc - nc - 2 * f];
-        recv[k] = v;
-    }
 }
 
 __global__ void scatter_kernel(int32_t n_pos, int32_t n_rows, int32_t alpha, const int32_t* __restrict__ perm_inv,
@@ -101,6 +78,148 @@ __global__ void symmetry_kernel(int32_t n_faces, int32_t n_iface, int32_t alpha,
         asym |= __double_as_longlong(recv[k]) != __double_as_longlong(recv[k2]);
     }
     if (asym) atomicOr(flags + 1, 1u);
+}
+
+// ---------------------------------------------------------------------------
+// Device-resident per-rank arrays: the receive buffer stays virtual.  Slot k
+// of rank s at local offset loc lies in that rank's diag, upper, lower or
+// interface array (table[4 s + region]); the gather reads it from there
+// instead of from a staged copy.  Positions are taken in contiguous chunks
+// per block, so one thread's successive positions (256 apart) almost always
+// come from the same rank, whose slot range each thread keeps in registers.
+// ---------------------------------------------------------------------------
+struct RankSlots {
+    int32_t s = -1, k_lo = 0, k_hi = 0, nc = 0, nf = 0;
+};
+
+__device__ __forceinline__ void rank_of_slot(RankSlots& r, int32_t k, int32_t alpha, const int32_t* slot_off,
+                                             const int32_t* row0, const int32_t* nf) {
+    if (k >= r.k_lo && k < r.k_hi) return;
+    r.s = find_block(slot_off, alpha, k);
+    r.k_lo = slot_off[r.s];
+    r.k_hi = slot_off[r.s + 1];
+    r.nc = row0[r.s + 1] - row0[r.s];
+    r.nf = nf[r.s];
+}
+
+// the value of slot k (rank r.s) from the per-rank arrays
+__device__ __forceinline__ double slot_value(const RankSlots& r, int32_t k, const double* const* table) {
+    const int32_t loc = k - r.k_lo;
+    int reg, base;
+    if (loc < r.nc) { reg = 0; base = 0; }
+    else if (loc < r.nc + r.nf) { reg = 1; base = r.nc; }
+    else if (loc < r.nc + 2 * r.nf) { reg = 2; base = r.nc + r.nf; }
+    else { reg = 3; base = r.nc + 2 * r.nf; }
+    return table[4 * r.s + reg][loc - base];
+}
+
+__device__ __forceinline__ void block_chunk(int64_t n, int32_t& a, int32_t& b) {
+    const int64_t per = ((n + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
+    const int64_t a64 = (int64_t)blockIdx.x * per;
+    a = (int32_t)(a64 < n ? a64 : n);
+    b = (int32_t)(a64 + per < n ? a64 + per : n);
+}
+
+// val64[j] = value of slot P^-1(j), val32 = RNE, dinv = 1 / diag, straight
+// from the per-rank arrays; same values and flags as scatter_kernel on the
+// staged buffer
+__global__ void __launch_bounds__(256)
+gather_kernel(int32_t n_pos, int32_t n_rows, int32_t alpha, const int32_t* __restrict__ perm_inv,
+              const double* const* __restrict__ table, const int32_t* __restrict__ slot_off,
+              const int32_t* __restrict__ row0, const int32_t* __restrict__ nf, double* __restrict__ val64,
+              float* __restrict__ val32, double* __restrict__ dinv64, float* __restrict__ dinv32,
+              uint32_t* flags) {
+    bool bad = false;
+    int32_t j0, j1;
+    block_chunk(n_pos, j0, j1);
+    RankSlots rs;
+    constexpr int U = 4;
+    int32_t j = j0 + threadIdx.x;
+    for (; j + (U - 1) * 256 < j1; j += U * 256) {
+        int32_t k[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) k[u] = perm_inv[j + u * 256];
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            rank_of_slot(rs, k[u], alpha, slot_off, row0, nf);
+            v[u] = slot_value(rs, k[u], table);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            __builtin_nontemporal_store(v[u], val64 + j + u * 256);
+            __builtin_nontemporal_store((float)v[u], val32 + j + u * 256);
+            bad |= !isfinite(v[u]);
+        }
+    }
+    for (; j < j1; j += 256) {
+        const int32_t k = perm_inv[j];
+        rank_of_slot(rs, k, alpha, slot_off, row0, nf);
+        const double v = slot_value(rs, k, table);
+        __builtin_nontemporal_store(v, val64 + j);
+        __builtin_nontemporal_store((float)v, val32 + j);
+        bad |= !isfinite(v);
+    }
+    int32_t i0, i1;
+    block_chunk(n_rows, i0, i1);
+    int32_t s = -1, lo = 0, hi = 0;
+    for (int32_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        if (i < lo || i >= hi) {
+            s = find_block(row0, alpha, i);
+            lo = row0[s];
+            hi = row0[s + 1];
+        }
+        const double d = table[4 * s][i - lo];
+        const double inv = 1.0 / d;
+        dinv64[i] = inv;
+        dinv32[i] = (float)inv;
+        bad |= !(d > 0.0) || !isfinite(d);
+    }
+    if (bad) atomicOr(flags, (uint32_t)FLAG_VALUE);
+}
+
+// symmetry_kernel on the per-rank arrays: flags[1] |= 1 when upper != lower
+// (check_faces) or an interface value differs from its partner's
+__global__ void __launch_bounds__(256)
+symmetry_gather_kernel(int32_t n_faces, int32_t n_iface, int32_t alpha, bool check_faces,
+                       const double* const* __restrict__ table, const int32_t* __restrict__ slot_off,
+                       const int32_t* __restrict__ row0, const int32_t* __restrict__ nf,
+                       const int32_t* __restrict__ face_off, const int32_t* __restrict__ iface_off,
+                       const int32_t* __restrict__ partner, uint32_t* flags) {
+    bool asym = false;
+    if (check_faces) {
+        int32_t f0, f1;
+        block_chunk(n_faces, f0, f1);
+        int32_t s = -1, lo = 0, hi = 0;
+        for (int32_t f = f0 + threadIdx.x; f < f1; f += 256) {
+            if (f < lo || f >= hi) {
+                s = find_block(face_off, alpha, f);
+                lo = face_off[s];
+                hi = face_off[s + 1];
+            }
+            asym |= __double_as_longlong(table[4 * s + 1][f - lo]) != __double_as_longlong(table[4 * s + 2][f - lo]);
+        }
+    }
+    int32_t e0, e1;
+    block_chunk(n_iface, e0, e1);
+    int32_t s = -1, lo = 0, hi = 0;
+    RankSlots rp;
+    for (int32_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        const int32_t k2 = partner[e];
+        if (k2 < 0) continue;
+        if (e < lo || e >= hi) {
+            s = find_block(iface_off, alpha, e);
+            lo = iface_off[s];
+            hi = iface_off[s + 1];
+        }
+        rank_of_slot(rp, k2, alpha, slot_off, row0, nf);
+        asym |= __double_as_longlong(table[4 * s + 3][e - lo]) != __double_as_longlong(slot_value(rp, k2, table));
+    }
+    if (asym) atomicOr(flags + 1, 1u);
+}
+
+__global__ void clear_flags(uint32_t* flags) {
+    if (threadIdx.x < 2) flags[threadIdx.x] = 0u;
 }
 
 int grid_for(int64_t n, int block = 256, int cap = 8192) {
@@ -162,24 +281,33 @@ int build_transpose(rp_plan* p, hipStream_t s) {
     return RP_OK;
 }
 
-int launch_stage_table(rp_plan* p, bool lower_given, hipStream_t s) {
-    for (int32_t s0 = 0; s0 < p->alpha; s0 += STAGE_RANKS) {
-        StageArgs a;
-        a.s0 = s0;
-        a.ns = std::min(STAGE_RANKS, p->alpha - s0);
-        for (int i = 0; i < a.ns; ++i) {
-            const int32_t r = s0 + i;
-            a.src[i][0] = p->h_src[4 * r + 0];
-            a.src[i][1] = p->h_src[4 * r + 1];
-            a.src[i][2] = lower_given ? p->h_src[4 * r + 2] : p->h_src[4 * r + 1];
-            a.src[i][3] = p->h_src[4 * r + 3];
-        }
-        const int64_t len = (int64_t)p->slot_off[s0 + a.ns] - p->slot_off[s0];
-        if (len == 0) continue;
-        hipLaunchKernelGGL(stage_kernel, dim3(grid_for(len)), dim3(256), 0, s, a, p->d_slot_off, p->d_row0,
-                           p->d_nf, p->d_recv);
+int launch_clear_flags(uint32_t* flags, hipStream_t s) {
+    hipLaunchKernelGGL(clear_flags, dim3(1), dim3(64), 0, s, flags);
+    RP_HIP_TRY(hipGetLastError());
+    return RP_OK;
+}
+
+int launch_update_gather(rp_plan* p, const double* const* table, bool lower_given, uint32_t* flags,
+                         hipStream_t s) {
+    int64_t total_faces = 0;
+    for (int32_t f : p->n_faces) total_faces += f;
+    const int64_t work = std::max<int64_t>(lower_given ? total_faces : 0, p->n_iface_share);
+    if (work > 0) {
+        hipLaunchKernelGGL(symmetry_gather_kernel, dim3(grid_for(work, 256, 2048)), dim3(256), 0, s,
+                           (int32_t)total_faces, (int32_t)p->n_iface_share, p->alpha, lower_given, table,
+                           p->d_slot_off, p->d_row0, p->d_nf, p->d_face_off, p->d_iface_off, p->d_iface_partner,
+                           flags);
         RP_HIP_TRY(hipGetLastError());
     }
+    const int64_t n_pos = p->n_slots;
+    if (n_pos == 0 && p->n_rows == 0) return RP_OK;
+    const int g = grid_for(std::max<int64_t>(n_pos, p->n_rows), 256, 2048);
+    RP_TRY(timing_begin(p, RP_KERNEL_SCATTER, s));
+    hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(256), 0, s, (int32_t)n_pos, (int32_t)p->n_rows, p->alpha,
+                       p->d_perm_inv, table, p->d_slot_off, p->d_row0, p->d_nf, p->d_val64, p->d_val32,
+                       p->d_dinv64, p->d_dinv32, flags);
+    RP_HIP_TRY(hipGetLastError());
+    RP_TRY(timing_end(p, RP_KERNEL_SCATTER, s));
     return RP_OK;
 }
 
