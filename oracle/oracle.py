@@ -55,6 +55,12 @@ def loaded_library():
         lib.or_bicgstab.argtypes = lib.or_pcg.argtypes
         lib.or_value_grad.argtypes = [C.c_int64, _I32, _I64, C.c_int64, C.c_int64, _F64, _F64, _F64]
         lib.or_face_grad.argtypes = [C.c_int64, _I64, _I64, _F64, _F64, _F64]
+        lib.or_block_starts.argtypes = [C.c_int, _I32, C.c_int, C.c_void_p]
+        lib.or_block_starts.restype = C.c_int64
+        lib.or_block_jacobi_inverse.argtypes = [_I32, _I32, _F64, C.c_int64, _I32, C.c_int, _F64]
+        lib.or_block_jacobi_apply.argtypes = [C.c_int64, _I32, C.c_int, _F64, _F64, _F64]
+        lib.or_pcg_block_jacobi.argtypes = [C.c_int64, _I32, _I32, _F64, C.c_int, _I32, C.c_int, _F64, _F64,
+                                            C.c_double, C.c_int64, C.c_int, _I64, _F64]
         _lib = lib
     return _lib
 
@@ -229,3 +235,59 @@ def face_grad(row_a, row_b, lam, x) -> np.ndarray:
     lib.or_face_grad(row_a.shape[0], row_a, row_b, np.ascontiguousarray(lam, dtype=np.float64),
                      np.ascontiguousarray(x, dtype=np.float64), g)
     return g[:row_a.shape[0]]
+
+
+def block_starts(n_cells_share, bs: int) -> np.ndarray:
+    """First fused row of every block-Jacobi block: each share rank's rows cut
+    into runs of bs (the last run of a rank may be shorter); last entry n_rows."""
+    lib = loaded_library()
+    nc = _i32(n_cells_share)
+    nb = lib.or_block_starts(len(nc), nc, int(bs), None)
+    start = np.zeros(nb + 1, np.int32)
+    lib.or_block_starts(len(nc), nc, int(bs), start.ctypes.data_as(C.c_void_p))
+    return start
+
+
+def block_jacobi_inverse(m: Merged, val64, start, bs: int) -> np.ndarray:
+    """Packed upper triangles of the Gauss-Jordan inverses of the diagonal
+    blocks (the block-Jacobi preconditioner, Sec. 5 outlook)."""
+    lib = loaded_library()
+    start = _i32(start)
+    nb = start.shape[0] - 1
+    minv = np.zeros(max(nb, 1) * (bs * (bs + 1) // 2))
+    st = lib.or_block_jacobi_inverse(m.row_ptr, _i32(m.col if m.nnz_local else np.zeros(1)),
+                                     np.ascontiguousarray(val64[:max(m.nnz_local, 1)], dtype=np.float64),
+                                     nb, start, int(bs), minv)
+    if st != 0:
+        raise OracleError(st, "block_jacobi_inverse")
+    return minv[:nb * (bs * (bs + 1) // 2)]
+
+
+def block_jacobi_apply(start, bs: int, minv, r) -> np.ndarray:
+    """z = M^-1 r with the packed block inverses."""
+    lib = loaded_library()
+    start = _i32(start)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    z = np.zeros(max(r.shape[0], 1))
+    lib.or_block_jacobi_apply(start.shape[0] - 1, start, int(bs),
+                              np.ascontiguousarray(minv, dtype=np.float64) if len(minv) else np.zeros(1),
+                              r if r.shape[0] else np.zeros(1), z)
+    return z[:r.shape[0]]
+
+
+def pcg_block_jacobi(m: Merged, val64, b, n_cells_share, bs: int, x0=None, tol=1e-8, max_iter=100000,
+                     max_restarts=5):
+    """PCG (as pcg) with the block-Jacobi preconditioner of block size bs.
+    Returns (x, status, iterations, restarts, true relative residual)."""
+    lib = loaded_library()
+    if m.nnz_nonlocal:
+        raise OracleError(-5, "pcg_block_jacobi (non-local block present)")
+    x = np.zeros(m.n_rows) if x0 is None else np.array(x0, dtype=np.float64)
+    out = np.zeros(2, np.int64)
+    res = np.zeros(1)
+    nc = _i32(n_cells_share)
+    st = lib.or_pcg_block_jacobi(m.n_rows, m.row_ptr, _i32(m.col),
+                                 np.ascontiguousarray(val64[:m.nnz_local], dtype=np.float64), len(nc), nc, int(bs),
+                                 np.ascontiguousarray(b, dtype=np.float64), x, float(tol), int(max_iter),
+                                 int(max_restarts), out, res)
+    return x, int(st), int(out[0]), int(out[1]), float(res[0])

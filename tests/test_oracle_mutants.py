@@ -48,6 +48,15 @@ MUTANTS = {
     "grad_transposed": ("-lambda[slot_row[k]] * x[c]", "-lambda[c] * x[slot_row[k]]"),
     # adjoint: interface face gradient sign of the partner term
     "face_grad_sign": ("-(lambda[a] - lambda[b]) * (x[a] - x[b])", "-(lambda[a] + lambda[b]) * (x[a] - x[b])"),
+    # block-Jacobi: only the rows below the pivot eliminated (no back elimination)
+    "bj_no_back_elimination": ("if (i == k) continue;\n                const double f = W[i][k];",
+                               "if (i <= k) continue;\n                const double f = W[i][k];"),
+    # block-Jacobi: packed store without the triangle offset
+    "bj_packed_index": ("out[i * bs - i * (i - 1) / 2 + (j - i)] = Z[i][j];", "out[i * bs + (j - i)] = Z[i][j];"),
+    # block-Jacobi: apply reads the row's entry for j < i from the wrong triangle
+    "bj_apply_wrong_triangle": ("const int a = i < j ? i : j, c = i < j ? j : i;", "const int a = i, c = j;"),
+    # block-Jacobi: blocks numbered from each rank's start instead of the share's
+    "bj_starts_rank_local": ("if (start) start[nb] = (int32_t)(row + c);", "if (start) start[nb] = (int32_t)c;"),
 }
 
 PIN_CALLS = [
@@ -65,6 +74,10 @@ PIN_CALLS = [
     lambda: [pins.test_p9_bicgstab_dense_lu(c) for c in range(1, len(pins.SMALL_CASES))],
     pins.test_p8_slot_gradient_dense,
     pins.test_p8_adjoint_face_gradient_finite_difference,
+    pins.test_p11_block_starts_hand_derived,
+    lambda: [pins.test_p11_block_inverse_against_lapack(c, bs) for c in range(len(pins.SMALL_CASES))
+             for bs in (2, 4)],
+    lambda: [pins.test_p11_apply_is_the_block_diagonal_solve(c, 4) for c in range(len(pins.SMALL_CASES))],
 ]
 
 

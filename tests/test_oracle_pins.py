@@ -530,3 +530,117 @@ def test_p8_reciprocity_identity():
     lam, *_ = oracle.pcg(m, val64, g, tol=1e-13)
     dx, *_ = oracle.pcg(m, val64, db, tol=1e-13)
     assert abs(lam @ db - g @ dx) <= 1e-10 * max(1.0, abs(lam @ db))
+
+
+# --------------------------------------------------------------------------
+# P11: block-Jacobi preconditioner (blocks of consecutive rows inside a rank)
+# --------------------------------------------------------------------------
+BJ_SIZES = [1, 2, 3, 4, 8]
+
+
+def _dense_share(w):
+    """The whole-share matrix built straight from the per-rank LDU arrays
+    (P2's brute force, independent of the oracle's merge)."""
+    vals = [dict(v, lower=v.get("lower", v["upper"])) for v in share_values(w)]
+    D, lo = _dense_from_ldu(w, vals, 0, w.n_ranks)
+    return D
+
+
+def _unpack(minv, b, bs, m):
+    """Block b of the packed store as a full m x m matrix: entry (i, j),
+    i <= j, at i*bs - i*(i-1)/2 + (j-i), mirrored below the diagonal."""
+    P = bs * (bs + 1) // 2
+    out = np.zeros((m, m))
+    for i in range(m):
+        for j in range(i, m):
+            out[i, j] = out[j, i] = minv[b * P + i * bs - i * (i - 1) // 2 + (j - i)]
+    return out
+
+
+def test_p11_block_starts_hand_derived():
+    # ranks of 5, 3, 0 and 4 rows, blocks of 2: no block crosses a rank
+    assert oracle.block_starts([5, 3, 0, 4], 2).tolist() == [0, 2, 4, 5, 7, 8, 10, 12]
+    assert oracle.block_starts([5, 3, 0, 4], 8).tolist() == [0, 5, 8, 12]
+    assert oracle.block_starts([5, 3, 0, 4], 1).tolist() == list(range(13))
+
+
+@pytest.mark.parametrize("case", range(len(SMALL_CASES)))
+@pytest.mark.parametrize("bs", BJ_SIZES)
+def test_p11_block_inverse_against_lapack(case, bs):
+    w = _small(case, seed=1100)
+    m, buf, val64, *_ = oracle_system(w)
+    D = _dense_share(w)
+    start = oracle.block_starts(w.part.n_cells, bs)
+    minv = oracle.block_jacobi_inverse(m, val64, start, bs)
+    for b in range(len(start) - 1):
+        s0, s1 = start[b], start[b + 1]
+        assert 1 <= s1 - s0 <= bs
+        Binv = np.linalg.inv(D[s0:s1, s0:s1])
+        got = _unpack(minv, b, bs, s1 - s0)
+        assert np.abs(got - Binv).max() <= 1e-12 * np.abs(Binv).max(), (b, got, Binv)
+
+
+@pytest.mark.parametrize("case", range(len(SMALL_CASES)))
+def test_p11_block_size_one_is_jacobi(case):
+    w = _small(case, seed=1200)
+    m, buf, val64, val32, d64, d32 = oracle_system(w)
+    start = oracle.block_starts(w.part.n_cells, 1)
+    minv = oracle.block_jacobi_inverse(m, val64, start, 1)
+    assert np.array_equal(_bits(minv), _bits(d64))          # 1 / diag, one IEEE division
+    b = w.rhs()
+    x1, st1, it1, *_ = oracle.pcg_block_jacobi(m, val64, b, w.part.n_cells, 1, tol=1e-10)
+    x0, st0, it0, *_ = oracle.pcg(m, val64, b, tol=1e-10)
+    assert st1 == st0 == 0 and abs(it1 - it0) <= 1
+    assert np.linalg.norm(x1 - x0) <= 1e-8 * np.linalg.norm(x0)
+
+
+@pytest.mark.parametrize("case", range(len(SMALL_CASES)))
+@pytest.mark.parametrize("bs", [2, 4, 8])
+def test_p11_apply_is_the_block_diagonal_solve(case, bs):
+    w = _small(case, seed=1300)
+    m, buf, val64, *_ = oracle_system(w)
+    D = _dense_share(w)
+    start = oracle.block_starts(w.part.n_cells, bs)
+    minv = oracle.block_jacobi_inverse(m, val64, start, bs)
+    r = np.random.default_rng(case).uniform(-1, 1, m.n_rows)
+    z = oracle.block_jacobi_apply(start, bs, minv, r)
+    want = np.concatenate([np.linalg.solve(D[s0:s1, s0:s1], r[s0:s1]) for s0, s1 in zip(start[:-1], start[1:])])
+    assert np.abs(z - want).max() <= 1e-12 * max(1.0, np.abs(want).max())
+
+
+def test_p11_one_block_is_the_exact_inverse():
+    """A single rank of 8 cells with blocks of 8: M = A, so PCG's first step
+    already solves the system."""
+    w = synth.small((2, 2, 2), ("blocks", 1, 1, 1), kappa=(1e-2, 1.0), seed=7)
+    m, buf, val64, *_ = oracle_system(w)
+    b = w.rhs()
+    x, st, it, rs, rr = oracle.pcg_block_jacobi(m, val64, b, w.part.n_cells, 8, tol=1e-13)
+    A = _dense_share(w)
+    assert st == 0 and it == 1
+    assert np.linalg.norm(x - np.linalg.solve(A, b)) <= 1e-13 * np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("case", range(1, len(SMALL_CASES)))
+@pytest.mark.parametrize("bs", [2, 4, 8])
+def test_p11_block_pcg_dense_lu(case, bs):
+    w = _small(case, seed=1400)
+    m, buf, val64, *_ = oracle_system(w)
+    A = _dense_share(w)
+    b = w.rhs()
+    xl = np.linalg.solve(A, b)
+    x, st, it, rs, rr = oracle.pcg_block_jacobi(m, val64, b, w.part.n_cells, bs, tol=1e-12)
+    assert st == 0 and rr <= 1e-12
+    assert np.linalg.norm(x - xl) <= 1e-8 * np.linalg.norm(xl)
+
+
+def test_p11_rejects_indefinite_block():
+    """diag 1, coupling -2 inside one block: the second pivot is -3."""
+    ranks = [dict(owner=np.array([0], np.int32), neighbour=np.array([1], np.int32),
+                  iface_cell=np.zeros(0, np.int32), iface_nbr_rank=np.zeros(0, np.int32),
+                  iface_nbr_cell=np.zeros(0, np.int32))]
+    m = oracle.merge([2], 0, 1, ranks)
+    v64, *_ = oracle.update(m, oracle.receive_buffer([dict(diag=[1.0, 1.0], upper=[-2.0], iface=[])]))
+    with pytest.raises(oracle.OracleError):
+        oracle.block_jacobi_inverse(m, v64, oracle.block_starts([2], 2), 2)
+    x, st, *_ = oracle.pcg_block_jacobi(m, v64, np.ones(2), [2], 2)
+    assert st == -6
