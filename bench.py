@@ -259,6 +259,27 @@ def main():
     n_spmv32, ms_spmv32 = plan.kernel_stats(RP_KERNEL_SPMV32)
     n_scat, ms_scat = plan.kernel_stats(RP_KERNEL_SCATTER)
     plan.set_timing(False)
+    # block-Jacobi preconditioner (blocks of consecutive rows inside a rank)
+    # against Jacobi on the same system: 3 timed solves each, after one warm-up
+    bj = {}
+    for label, kw in (("jacobi", dict(precision="fp64")),
+                      ("block_jacobi_4", dict(precision="fp64", precond="block_jacobi", block_size=4)),
+                      ("block_jacobi_8", dict(precision="fp64", precond="block_jacobi", block_size=8)),
+                      ("mixed_block_jacobi_4", dict(precision="mixed", precond="block_jacobi", block_size=4))):
+        plan.solve(b, opts=default_opts(tol=1e-8, x0_zero=1, **kw))
+        ts, its = [], []
+        for _ in range(3):
+            e_a = ev()
+            _, ib = plan.solve(b, opts=default_opts(tol=1e-8, x0_zero=1, **kw))
+            e_b = ev()
+            torch.cuda.synchronize()
+            assert ib["status"] == 0 and ib["rel_res"] <= 1e-8, ib
+            ts.append(e_a.elapsed_time(e_b))
+            its.append(ib["iters"])
+        bj[label] = {"ms_per_solve": round(float(np.median(ts)), 3), "iters": int(np.median(its))}
+    for label in bj:
+        bj[label]["speedup_vs_jacobi"] = round(bj["jacobi"]["ms_per_solve"] / bj[label]["ms_per_solve"], 3)
+    print(f"[bench] preconditioners: {bj}", flush=True)
 
     el = lambda e_a, e_b: e_a.elapsed_time(e_b)
     upd = [el(r["ev"][0], r["ev"][1]) for r in recs]
@@ -341,6 +362,8 @@ def main():
                      "fp64_updates": int(last["mixed_rr"]["outer_iters"]),
                      "speedup_vs_fp64": round(med(f64) / med(mr), 3)},
         "restarts_in_timed_solves": restarts,
+        "preconditioners": dict(bj, note="last timestep's system, x0 = 0, tol 1e-8, 3 solves each (median); "
+                                         "block_jacobi_b: blocks of b consecutive rows inside each rank"),
         "fp64_warm_start": ({"ms_per_solve": round(float(np.median([wm for wm, _ in warm])), 3),
                              "iters": int(np.median([wi for _, wi in warm])),
                              "note": "x0 = previous timestep's x; values differ by up to 5 % between timesteps"}

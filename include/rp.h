@@ -70,6 +70,12 @@ extern "C" {
 #define RP_MIXED_RR 3             /* FP32 PCG with FP64 residual replacement every
                                      update_delta reduction (solve only) */
 
+/* ---- preconditioners ---------------------------------------------------- */
+#define RP_PRECOND_JACOBI 0       /* M = diag(A) */
+#define RP_PRECOND_BLOCK_JACOBI 1 /* M = the diagonal blocks of block_size consecutive rows,
+                                     every block inside one CPU rank (CG only) */
+#define RP_BJ_MAX_BLOCK 8
+
 /* ---- Krylov methods ------------------------------------------------------ */
 #define RP_CG 0                   /* Jacobi-PCG, symmetric positive definite A (the pressure
                                      system, Sec. 4) */
@@ -118,6 +124,9 @@ typedef struct rp_solve_opts {
                                 off where launches, not the SpMV, bound an iteration.
                                 Ignored while kernel timing is on and by RP_BICGSTAB
                                 (default 0) */
+    int32_t precond;         /* RP_PRECOND_JACOBI (default) or RP_PRECOND_BLOCK_JACOBI
+                                (RP_CG, fused solve order; FP64 and both mixed forms) */
+    int32_t block_size;      /* block-Jacobi rows per block, 1..RP_BJ_MAX_BLOCK (default 4) */
 } rp_solve_opts;
 
 typedef struct rp_solve_info {
@@ -170,7 +179,9 @@ typedef struct rp_device_ptrs {
     const float* val32;         /* [n_slots] RNE copy of val64 */
     const double* dinv64;       /* [n_rows] 1 / diag */
     const float* dinv32;        /* [n_rows] RNE copy of dinv64 */
-    const double* recv;         /* [n_slots] receive buffer, slot order */
+    const double* recv;         /* [n_slots] receive buffer, slot order: holds the
+                                   values of the last update from host memory
+                                   (device-resident rank arrays are read in place) */
 } rp_device_ptrs;
 int rp_plan_device_ptrs(const rp_plan* plan, rp_device_ptrs* out);
 
@@ -262,6 +273,7 @@ int rp_update_values(rp_plan* plan, const double* const* diag, const double* con
  * ranks write straight into when they can reach device memory). */
 int rp_update_values_slots(rp_plan* plan, const double* slots, void* stream);
 
+
 /* ---- kernels on the fused matrix ---------------------------------------- *
  * y = A x over the local block, x and y device arrays of n_rows elements:
  * double with RP_FP64, float with RP_FP32.  Each row is summed from 0 in
@@ -305,6 +317,23 @@ void rp_solve_opts_default(rp_solve_opts* opts);
  * gradients of a face. */
 int rp_value_grad(rp_plan* plan, const double* lambda, const double* x, double* g_slots,
                   void* stream);
+
+/* Block-Jacobi preconditioner (the stronger preconditioner of the outlook in
+ * Sec. 5), with every block inside one CPU rank: each share rank's fused
+ * rows are cut into runs of block_size consecutive rows (a rank's last run
+ * may be shorter), and M = blockdiag(A_bb).  Each diagonal block is inverted
+ * by Gauss-Jordan elimination without pivoting (pivots in order; A is SPD),
+ * and the upper triangle of the inverse serves both triangles, so M^-1 is
+ * exactly symmetric.  Built on the GPU by the first solve that asks for it
+ * after each update; this call builds it for the current values (it
+ * synchronises) and copies it out (any output may be NULL): n_blocks,
+ * start[n_blocks+1] (first fused row of each block), and the packed upper
+ * triangles minv64 / minv32 [n_blocks * P], P = bs (bs + 1) / 2, entry
+ * (i, j), i <= j < rows of the block, at b * P + i bs - i (i - 1) / 2 + j - i
+ * (unused entries 0; minv32 = RNE(minv64)).  RP_ERR_BREAKDOWN when a block
+ * is not positive definite. */
+int rp_plan_block_jacobi(rp_plan* plan, int32_t block_size, int64_t* n_blocks, int32_t* start,
+                         double* minv64, float* minv32);
 
 /* Launch shape of the solvers' elementwise kernels (a diagnostic knob; the
  * default sizes the grid to n_rows, at most 1024 blocks).  blocks = 0 restores

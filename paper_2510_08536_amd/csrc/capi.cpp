@@ -78,7 +78,8 @@ void free_plan(rp_plan* p) {
                    p->d_flags, p->d_goi_k, p->d_goi_off, p->d_goi_mask, p->d_bi_st, p->d_bi_work,
                    p->d_valT, p->d_tflag, p->d_ro_perm, p->d_ro_row_ptr, p->d_ro_col, p->d_ro_sig,
                    p->d_ro_val64, p->d_ro_val32, p->d_ro_dinv64, p->d_ro_dinv32, p->d_ro_b, p->d_ro_x,
-                   p->d_ro_valT, (void*)p->d_src};
+                   p->d_ro_valT, (void*)p->d_src, p->d_bj_start, p->d_bj_minv64, p->d_bj_minv32, p->d_z,
+                   p->d_z32, p->d_bj_flag};
     for (void* q : dev)
         if (q) (void)hipFree(q);
     if (p->h_st64) (void)hipHostFree(p->h_st64);
@@ -386,6 +387,23 @@ int rp_plan_device_ptrs(const rp_plan* p, rp_device_ptrs* out) {
     return RP_OK;
 }
 
+int rp_plan_block_jacobi(rp_plan* p, int32_t block_size, int64_t* n_blocks, int32_t* start, double* minv64,
+                         float* minv32) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    RP_CHECK(p->has_values, RP_ERR_ARG, "no values yet: call rp_update_values first");
+    RP_TRY(activate(p));
+    hipStream_t s = p->last_stream;
+    RP_TRY(bj_prepare(p, block_size, s));
+    RP_HIP_TRY(hipStreamSynchronize(s));
+    const int64_t nb = p->bj_blocks, P = (int64_t)block_size * (block_size + 1) / 2;
+    if (n_blocks) *n_blocks = nb;
+    if (start) RP_HIP_TRY(hipMemcpy(start, p->d_bj_start, sizeof(int32_t) * (nb + 1), hipMemcpyDeviceToHost));
+    if (minv64 && nb) RP_HIP_TRY(hipMemcpy(minv64, p->d_bj_minv64, sizeof(double) * nb * P, hipMemcpyDeviceToHost));
+    if (minv32 && nb) RP_HIP_TRY(hipMemcpy(minv32, p->d_bj_minv32, sizeof(float) * nb * P, hipMemcpyDeviceToHost));
+    return RP_OK;
+}
+
 int rp_plan_set_vec_grid(rp_plan* p, int32_t blocks) {
     clear_error();
     RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
@@ -454,6 +472,8 @@ void rp_solve_opts_default(rp_solve_opts* o) {
     o->method = RP_CG;
     o->transpose = 0;
     o->graph = 0;
+    o->precond = RP_PRECOND_JACOBI;
+    o->block_size = 4;
 }
 
 int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, rp_solve_info* info,
@@ -477,6 +497,14 @@ int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, 
     RP_CHECK(o.method == RP_CG || o.precision == RP_FP64, RP_ERR_UNSUPPORTED, "BiCGStab runs in FP64 only");
     RP_CHECK(o.transpose == 0 || o.transpose == 1, RP_ERR_ARG, "transpose must be 0 or 1");
     RP_CHECK(o.graph == 0 || o.graph == 1, RP_ERR_ARG, "graph must be 0 or 1");
+    RP_CHECK(o.precond == RP_PRECOND_JACOBI || o.precond == RP_PRECOND_BLOCK_JACOBI, RP_ERR_ARG,
+             "precond must be RP_PRECOND_JACOBI or RP_PRECOND_BLOCK_JACOBI");
+    RP_CHECK(o.precond == RP_PRECOND_JACOBI || (o.block_size >= 1 && o.block_size <= RP_BJ_MAX_BLOCK), RP_ERR_ARG,
+             "block_size must be in 1..%d", RP_BJ_MAX_BLOCK);
+    RP_CHECK(o.precond == RP_PRECOND_JACOBI || o.method == RP_CG, RP_ERR_UNSUPPORTED,
+             "block-Jacobi is built for CG (RP_CG) only");
+    RP_CHECK(o.precond == RP_PRECOND_JACOBI || p->ro_mode == 0, RP_ERR_UNSUPPORTED,
+             "block-Jacobi runs in the fused row order only (solve order 0)");
     RP_TRY(activate(p));
     hipStream_t s = as_stream(stream);
     p->last_stream = s;

@@ -267,11 +267,11 @@ cg_update_r(int32_t n, int32_t k_arg, int32_t g_spmv, T* __restrict__ r, const T
 // (partials from cg_rz_rr): x already holds this iteration's step, the stop
 // tests are skipped.  Runs only when K2 completed this iteration (kk); block
 // 0 records a stop in `done`, which K3 itself never reads.
-template <typename T>
+template <typename T, bool ZMEM>
 __global__ void __launch_bounds__(VEC_BLOCK)
 cg_update_xp(int32_t n, int32_t k_arg, int32_t g_vec, int32_t resume, const T* __restrict__ r,
-             const T* __restrict__ dinv, T* __restrict__ x, T* __restrict__ p, const T* __restrict__ part,
-             CgState<T>* st) {
+             const T* __restrict__ dinv, const T* __restrict__ z, T* __restrict__ x, T* __restrict__ p,
+             const T* __restrict__ part, CgState<T>* st) {
 #pragma clang fp contract(off)
     // iteration number: the argument, or the one K2 of this iteration wrote
     int32_t k = k_arg;
@@ -301,30 +301,36 @@ cg_update_xp(int32_t n, int32_t k_arg, int32_t g_vec, int32_t resume, const T* _
         return;
     }
     const T beta = rz / st->rz[k & 3];
+    // z = M^-1 r: Jacobi on the fly, or (ZMEM) as the block-Jacobi kernel
+    // before this one stored it
     if (resume) {
-        for (int32_t i = i0; i < n; i += di) p[i] = dinv[i] * r[i] + beta * p[i];
+        for (int32_t i = i0; i < n; i += di) p[i] = (ZMEM ? z[i] : dinv[i] * r[i]) + beta * p[i];
     } else {
         int32_t i = i0;
         constexpr int U = vec_unroll_xp<T>();
         for (; (int64_t)i + (int64_t)(U - 1) * di < n; i += U * di) {
-            T rv[U], dv[U], xv[U], pv[U];
+            T zv[U], xv[U], pv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                rv[u] = r[i + u * di];
-                dv[u] = dinv[i + u * di];
+                if (ZMEM) {
+                    zv[u] = z[i + u * di];
+                } else {
+                    const T ri = r[i + u * di];
+                    zv[u] = dinv[i + u * di] * ri;
+                }
                 xv[u] = x[i + u * di];
                 pv[u] = p[i + u * di];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 x[i + u * di] = xv[u] + a * pv[u];
-                p[i + u * di] = dv[u] * rv[u] + beta * pv[u];
+                p[i + u * di] = zv[u] + beta * pv[u];
             }
         }
         for (; i < n; i += di) {
             const T pi = p[i];
             x[i] = x[i] + a * pi;
-            p[i] = dinv[i] * r[i] + beta * pi;
+            p[i] = (ZMEM ? z[i] : dinv[i] * r[i]) + beta * pi;
         }
     }
     if (lead) {
@@ -349,6 +355,143 @@ ir_accumulate(int32_t n, double* __restrict__ x, float* __restrict__ d) {
         d[i] = 0.0f;
     }
 }
+
+// ---------------------------------------------------------------------------
+// block-Jacobi forms of the kernels that apply M^-1 (blocks of BS rows, one
+// thread per block; packed inverses from precond.hip).  z_i sums over the
+// block's j ascending, from 0, as the definition does.
+// ---------------------------------------------------------------------------
+template <int BS>
+__device__ __forceinline__ constexpr int bj_idx(int i, int j) {
+    return i <= j ? i * BS - i * (i - 1) / 2 + (j - i) : j * BS - j * (j - 1) / 2 + (i - j);
+}
+
+// zv[0..m) = M_b^-1 rv[0..m) for block b
+template <typename T, int BS>
+__device__ __forceinline__ void bj_block_solve(int32_t m, const T* __restrict__ mb, const T (&rv)[BS], T (&zv)[BS]) {
+#pragma clang fp contract(off)
+    constexpr int P = BS * (BS + 1) / 2;
+    T pk[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) pk[q] = mb[q];
+#pragma unroll
+    for (int i = 0; i < BS; ++i) {
+        T s = T(0);
+#pragma unroll
+        for (int j = 0; j < BS; ++j)
+            if (j < m) s += pk[bj_idx<BS>(i, j)] * rv[j];
+        zv[i] = s;
+    }
+}
+
+// K2 with block-Jacobi: alpha = rz_k / (p, q); r -= alpha q; z = M^-1 r
+// (stored for K3); partials of (r, z) -> PART_RZ and (r, r) -> PART_RR
+template <typename T, int BS>
+__global__ void __launch_bounds__(VEC_BLOCK)
+cg_update_r_bj(int32_t n, int32_t k_arg, int32_t g_spmv, int32_t nb, const int32_t* __restrict__ start,
+               const T* __restrict__ minv, T* __restrict__ r, const T* __restrict__ q, T* __restrict__ z,
+               T* __restrict__ part, CgState<T>* st) {
+#pragma clang fp contract(off)
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (st->done != CG_RUNNING) {
+        if (lead) st->kk = -1;
+        return;
+    }
+    const int32_t k = k_arg >= 0 ? k_arg : st->iter;
+    if (k >= st->max_iter) {
+        if (lead) st->kk = -1;
+        return;
+    }
+    __shared__ T red[VEC_BLOCK / 64];
+    const T pq = sum_partials_all<T, VEC_BLOCK>(part + PART_A, g_spmv, red);
+    if (!(pq > T(0)) || !isfinite(pq)) {
+        if (lead) {
+            st->pq = pq;
+            st->iter = k;
+            st->kk = -1;
+            st->done = CG_BREAKDOWN;
+        }
+        return;
+    }
+    const T a = st->rz[k & 3] / pq;
+    constexpr int P = BS * (BS + 1) / 2;
+    T prz = T(0), prr = T(0);
+    for (int32_t b = blockIdx.x * VEC_BLOCK + threadIdx.x; b < nb; b += gridDim.x * VEC_BLOCK) {
+        const int32_t s0 = start[b], m = start[b + 1] - s0;
+        T rv[BS], zv[BS];
+#pragma unroll
+        for (int j = 0; j < BS; ++j) {
+            rv[j] = T(0);
+            if (j < m) rv[j] = r[s0 + j] - a * q[s0 + j];
+        }
+        bj_block_solve<T, BS>(m, minv + (int64_t)b * P, rv, zv);
+#pragma unroll
+        for (int j = 0; j < BS; ++j)
+            if (j < m) {
+                r[s0 + j] = rv[j];
+                z[s0 + j] = zv[j];
+                prz += rv[j] * zv[j];
+                prr += rv[j] * rv[j];
+            }
+    }
+    const T b1 = block_sum<T, VEC_BLOCK>(prz, red);
+    const T b2 = block_sum<T, VEC_BLOCK>(prr, red);
+    if (threadIdx.x == 0) {
+        part[PART_RZ + blockIdx.x] = b1;
+        part[PART_RR + blockIdx.x] = b2;
+    }
+    if (lead) {
+        st->pq = pq;
+        st->alpha = a;
+        st->kk = k;
+    }
+}
+
+// start with block-Jacobi: p = M^-1 r; partials of (r, M^-1 r) -> PART_RZ.
+// rz_rr: z = M^-1 r stored, partials of (r, z) -> PART_RZ and (r, r) -> PART_RR
+template <typename T, int BS, bool RZ_RR>
+__global__ void __launch_bounds__(VEC_BLOCK)
+cg_precond_bj(int32_t nb, const int32_t* __restrict__ start, const T* __restrict__ minv, const T* __restrict__ r,
+              T* __restrict__ out, T* __restrict__ part) {
+#pragma clang fp contract(off)
+    __shared__ T red[VEC_BLOCK / 64];
+    constexpr int P = BS * (BS + 1) / 2;
+    T prz = T(0), prr = T(0);
+    for (int32_t b = blockIdx.x * VEC_BLOCK + threadIdx.x; b < nb; b += gridDim.x * VEC_BLOCK) {
+        const int32_t s0 = start[b], m = start[b + 1] - s0;
+        T rv[BS], zv[BS];
+#pragma unroll
+        for (int j = 0; j < BS; ++j) rv[j] = j < m ? r[s0 + j] : T(0);
+        bj_block_solve<T, BS>(m, minv + (int64_t)b * P, rv, zv);
+#pragma unroll
+        for (int j = 0; j < BS; ++j)
+            if (j < m) {
+                out[s0 + j] = zv[j];
+                prz += rv[j] * zv[j];
+                prr += rv[j] * rv[j];
+            }
+    }
+    const T b1 = block_sum<T, VEC_BLOCK>(prz, red);
+    if (RZ_RR) {
+        const T b2 = block_sum<T, VEC_BLOCK>(prr, red);
+        if (threadIdx.x == 0) part[PART_RR + blockIdx.x] = b2;
+    }
+    if (threadIdx.x == 0) part[PART_RZ + blockIdx.x] = b1;
+}
+
+#define RP_DISPATCH_BS(bs, CALL) \
+    do {                         \
+        switch (bs) {            \
+        case 1: CALL(1); break;  \
+        case 2: CALL(2); break;  \
+        case 3: CALL(3); break;  \
+        case 4: CALL(4); break;  \
+        case 5: CALL(5); break;  \
+        case 6: CALL(6); break;  \
+        case 7: CALL(7); break;  \
+        default: CALL(8); break; \
+        }                        \
+    } while (0)
 
 __global__ void fill_zero(int32_t n, double* x) {
     for (int32_t i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK) x[i] = 0.0;
@@ -377,6 +520,12 @@ struct Cg {
     int32_t g_spmv, g_vec;
     int32_t xw_mode;
     XWin w;
+    // block-Jacobi (bj_minv != nullptr): M^-1 by blocks; z holds M^-1 r for K3
+    const int32_t* bj_start = nullptr;
+    const T* bj_minv = nullptr;
+    int32_t bj_nb = 0;
+    int32_t bj_bs = 0;
+    T* z = nullptr;
 };
 
 // the matrix a solve runs on: the fused pattern in the plan's SpMV form, or
@@ -435,7 +584,15 @@ int launch_finalize(Cg<T>& c, int32_t mode, int32_t k, T tol2, T pause_frac2, in
 // partials are still in PART_A / PART_B)
 template <typename T>
 int launch_start(Cg<T>& c, int32_t k, T tol2, T pause_frac2, int32_t max_iter) {
-    hipLaunchKernelGGL(cg_start_p<T>, dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, c.r, c.dinv, c.p, c.part);
+    if (c.bj_minv) {
+#define RP_LAUNCH(BS)                                                                                          \
+    hipLaunchKernelGGL((cg_precond_bj<T, BS, false>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.bj_nb, c.bj_start, \
+                       c.bj_minv, c.r, c.p, c.part)
+        RP_DISPATCH_BS(c.bj_bs, RP_LAUNCH);
+#undef RP_LAUNCH
+    } else {
+        hipLaunchKernelGGL(cg_start_p<T>, dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, c.r, c.dinv, c.p, c.part);
+    }
     RP_HIP_TRY(hipGetLastError());
     return launch_finalize(c, FIN_START, k, tol2, pause_frac2, max_iter);
 }
@@ -444,9 +601,19 @@ int launch_start(Cg<T>& c, int32_t k, T tol2, T pause_frac2, int32_t max_iter) {
 template <typename T>
 int launch_resume(Cg<T>& c) {
     const int32_t k = c.h->iter - 1;
-    hipLaunchKernelGGL(cg_rz_rr<T>, dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, c.r, c.dinv, c.part);
-    hipLaunchKernelGGL(cg_update_xp<T>, dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, k, c.g_vec, 1, c.r, c.dinv,
-                       c.x, c.p, c.part, c.st);
+    if (c.bj_minv) {
+#define RP_LAUNCH(BS)                                                                                         \
+    hipLaunchKernelGGL((cg_precond_bj<T, BS, true>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.bj_nb, c.bj_start, \
+                       c.bj_minv, c.r, c.z, c.part)
+        RP_DISPATCH_BS(c.bj_bs, RP_LAUNCH);
+#undef RP_LAUNCH
+        hipLaunchKernelGGL((cg_update_xp<T, true>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, k, c.g_vec, 1, c.r,
+                           c.dinv, c.z, c.x, c.p, c.part, c.st);
+    } else {
+        hipLaunchKernelGGL(cg_rz_rr<T>, dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, c.r, c.dinv, c.part);
+        hipLaunchKernelGGL((cg_update_xp<T, false>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, k, c.g_vec, 1, c.r,
+                           c.dinv, c.z, c.x, c.p, c.part, c.st);
+    }
     RP_HIP_TRY(hipGetLastError());
     return RP_OK;
 }
@@ -462,8 +629,19 @@ int launch_iteration(Cg<T>& c, int32_t k, hipStream_t s) {
     RP_DISPATCH_NW(c.xw_mode, RP_LAUNCH);
 #undef RP_LAUNCH
     RP_TRY(timing_end(c.plan, c.kernel_id, s));
-    hipLaunchKernelGGL(cg_update_r<T>, gv, bv, 0, s, c.n, k, c.g_spmv, c.r, c.q, c.dinv, c.part, c.st);
-    hipLaunchKernelGGL(cg_update_xp<T>, gv, bv, 0, s, c.n, k, c.g_vec, 0, c.r, c.dinv, c.x, c.p, c.part, c.st);
+    if (c.bj_minv) {
+#define RP_LAUNCH(BS)                                                                                          \
+    hipLaunchKernelGGL((cg_update_r_bj<T, BS>), gv, bv, 0, s, c.n, k, c.g_spmv, c.bj_nb, c.bj_start, c.bj_minv, \
+                       c.r, c.q, c.z, c.part, c.st)
+        RP_DISPATCH_BS(c.bj_bs, RP_LAUNCH);
+#undef RP_LAUNCH
+        hipLaunchKernelGGL((cg_update_xp<T, true>), gv, bv, 0, s, c.n, k, c.g_vec, 0, c.r, c.dinv, c.z, c.x, c.p,
+                           c.part, c.st);
+    } else {
+        hipLaunchKernelGGL(cg_update_r<T>, gv, bv, 0, s, c.n, k, c.g_spmv, c.r, c.q, c.dinv, c.part, c.st);
+        hipLaunchKernelGGL((cg_update_xp<T, false>), gv, bv, 0, s, c.n, k, c.g_vec, 0, c.r, c.dinv, c.z, c.x, c.p,
+                           c.part, c.st);
+    }
     RP_HIP_TRY(hipGetLastError());
     return RP_OK;
 }
@@ -482,7 +660,9 @@ int cg_graph(Cg<T>& c, int chunk, hipGraphExec_t* out) {
                               (uint64_t)(uintptr_t)c.ix.col, (uint64_t)(uintptr_t)c.ix.goi_k,
                               (uint64_t)(uintptr_t)c.ix.goi_off, (uint64_t)(uintptr_t)c.ix.goi_mask,
                               (uint64_t)c.g_spmv,       (uint64_t)c.g_vec,      (uint64_t)(uint32_t)c.xw_mode,
-                              (uint64_t)(uint32_t)c.w.d[0], (uint64_t)(uint32_t)c.w.d[1], 1, 0, 0, 0};
+                              (uint64_t)(uint32_t)c.w.d[0], (uint64_t)(uint32_t)c.w.d[1],
+                              (uint64_t)(uintptr_t)c.bj_minv, (uint64_t)(uintptr_t)c.bj_start,
+                              (uint64_t)(uintptr_t)c.z, ((uint64_t)(uint32_t)c.bj_nb << 8) | (uint32_t)c.bj_bs};
     if (g.exec && std::memcmp(g.key, key, sizeof key) == 0) {
         *out = g.exec;
         return RP_OK;
@@ -534,6 +714,16 @@ int iterate(Cg<T>& c, int chunk, int32_t max_iter, bool graph) {
     return RP_OK;
 }
 
+// block-Jacobi for this solve when the options ask for it
+template <typename T>
+void use_block_jacobi(Cg<T>& c, const rp_plan* p, const T* minv, T* z) {
+    c.bj_start = p->d_bj_start;
+    c.bj_minv = minv;
+    c.bj_nb = (int32_t)p->bj_blocks;
+    c.bj_bs = p->bj_bs;
+    c.z = z;
+}
+
 int pending_value_error(rp_plan* p, hipStream_t s, bool need_symmetric) {
     RP_HIP_TRY(hipMemcpyAsync(p->h_flags, p->d_flags, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     RP_HIP_TRY(hipStreamSynchronize(s));
@@ -571,6 +761,10 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
     Cg<double> c = make_cg<double>(p, m, ordered ? p->d_ro_val64 : p->d_val64,
                                    ordered ? p->d_ro_dinv64 : p->d_dinv64, x, b, p->d_r, p->d_p, p->d_q,
                                    p->d_st64, p->h_st64, RP_KERNEL_SPMV64, s);
+    if (o.precond == RP_PRECOND_BLOCK_JACOBI) {
+        RP_TRY(bj_prepare(p, o.block_size, s));
+        use_block_jacobi(c, p, p->d_bj_minv64, p->d_z);
+    }
     const double tol2 = o.tol * o.tol;
     const int chunk = std::max(1, o.check_every);
     RP_TRY((launch_residual<double, false>(c, o.x0_zero != 0, nullptr)));
@@ -639,6 +833,10 @@ int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, 
     Cg<float> in = make_cg<float>(p, m, ordered ? p->d_ro_val32 : p->d_val32,
                                   ordered ? p->d_ro_dinv32 : p->d_dinv32, p->d_x32, p->d_r32, p->d_r32, p->d_p32,
                                   p->d_q32, p->d_st32, p->h_st32, RP_KERNEL_SPMV32, s);
+    if (o.precond == RP_PRECOND_BLOCK_JACOBI) {
+        RP_TRY(bj_prepare(p, o.block_size, s));
+        use_block_jacobi(in, p, p->d_bj_minv32, p->d_z32);
+    }
     const int chunk = std::max(1, o.check_every);
 
     RP_TRY((launch_residual<double, true>(out, o.x0_zero != 0, p->d_r32)));

@@ -110,6 +110,7 @@ constexpr int vec_unroll_r() { return sizeof(T) == 8 ? 4 : 2; }
 template <typename T>
 constexpr int vec_unroll_xp() { return sizeof(T) == 8 ? 4 : 1; }
 constexpr int N_XCD = 8;                      // MI355X: 8 accelerator dies
+constexpr int BJ_MAX = RP_BJ_MAX_BLOCK;       // largest block-Jacobi block
 
 // ---------------------------------------------------------------------------
 // plan
@@ -220,6 +221,18 @@ struct rp_plan {
     std::vector<int32_t> h_ro_perm;
     int64_t ro_version = -1;           // values_version the solve-order values were gathered from
 
+    // block-Jacobi preconditioner (precond.hip), built on first use for a
+    // block size and rebuilt after every update
+    int32_t bj_bs = 0;                 // block size of the tables below (0: none)
+    int64_t bj_blocks = 0;
+    int64_t bj_version = -1;           // values_version the inverses were built from
+    int32_t* d_bj_start = nullptr;     // [bj_blocks + 1] first fused row of each block
+    double* d_bj_minv64 = nullptr;     // [bj_blocks * bs (bs + 1) / 2] packed upper triangles
+    float* d_bj_minv32 = nullptr;      // RNE copy
+    double* d_z = nullptr;             // [n_rows] z = M^-1 r of the FP64 iteration
+    float* d_z32 = nullptr;            // [n_rows] of the FP32 iteration
+    uint32_t* d_bj_flag = nullptr;     // set when a block is not positive definite
+
     // captured CG iteration chunks (rp_solve_opts.graph), [0] FP64, [1] FP32
     hipStream_t capture_stream = nullptr;
     struct CgGraph {
@@ -296,6 +309,9 @@ int solve_bicgstab(rp_plan* p, const double* b, double* x, const rp_solve_opts& 
 int build_transpose(rp_plan* p, hipStream_t s);
 int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
                 hipStream_t s, bool reliable, bool ordered = false);
+// precond.hip
+// block-Jacobi tables and inverses for block size bs, current for the values
+int bj_prepare(rp_plan* p, int32_t bs, hipStream_t s);
 // order.hip
 // reverse Cuthill-McKee order of a structurally symmetric pattern: perm[k] = row at position k
 std::vector<int32_t> rcm_order(int32_t n, const int32_t* row_ptr, const int32_t* col);

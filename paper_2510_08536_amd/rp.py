@@ -48,7 +48,9 @@ EXPORTED = ["rp_plan_create", "rp_plan_destroy", "rp_plan_sizes", "rp_plan_get_c
             "rp_update_values", "rp_update_values_slots", "rp_spmv", "rp_solve", "rp_solve_opts_default",
             "rp_value_grad", "rp_sync", "rp_last_error", "rp_plan_set_timing", "rp_plan_kernel_stats",
             "rp_plan_set_solve_order", "rp_plan_solve_order", "rp_rcm_order", "rp_plan_device_ptrs",
-            "rp_plan_set_vec_grid"]
+            "rp_plan_set_vec_grid", "rp_plan_block_jacobi"]
+RP_PRECOND_JACOBI, RP_PRECOND_BLOCK_JACOBI = 0, 1
+RP_BJ_MAX_BLOCK = 8
 
 
 class rp_rank_desc(C.Structure):
@@ -63,7 +65,7 @@ class rp_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("inner_tol", C.c_double), ("update_delta", C.c_double), ("max_iter", C.c_int32),
                 ("precision", C.c_int32), ("max_outer", C.c_int32), ("check_every", C.c_int32),
                 ("x0_zero", C.c_int32), ("max_restarts", C.c_int32), ("method", C.c_int32),
-                ("transpose", C.c_int32), ("graph", C.c_int32)]
+                ("transpose", C.c_int32), ("graph", C.c_int32), ("precond", C.c_int32), ("block_size", C.c_int32)]
 
 
 class rp_solve_info(C.Structure):
@@ -123,6 +125,7 @@ _sig = {
     "rp_rcm_order": (C.c_int, [C.c_int32, _P, _P, _P]),
     "rp_plan_device_ptrs": (C.c_int, [_P, C.POINTER(rp_device_ptrs)]),
     "rp_plan_set_vec_grid": (C.c_int, [_P, C.c_int32]),
+    "rp_plan_block_jacobi": (C.c_int, [_P, C.c_int32, _i64p, _P, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -186,6 +189,8 @@ def _set_opts(o: rp_solve_opts, **kw) -> rp_solve_opts:
             v = {"fp64": RP_FP64, "mixed": RP_MIXED, "mixed_rr": RP_MIXED_RR}[v]
         if k == "method" and isinstance(v, str):
             v = {"cg": RP_CG, "bicgstab": RP_BICGSTAB}[v]
+        if k == "precond" and isinstance(v, str):
+            v = {"jacobi": RP_PRECOND_JACOBI, "block_jacobi": RP_PRECOND_BLOCK_JACOBI}[v]
         setattr(o, k, v)
     return o
 
@@ -310,6 +315,19 @@ class Plan:
         d = rp_device_ptrs()
         _check(rp_plan_device_ptrs(self._h, C.byref(d)), "rp_plan_device_ptrs")
         return d.as_dict()
+
+    def block_jacobi(self, block_size: int):
+        """(start, minv64, minv32) of the block-Jacobi preconditioner for the
+        current values (built on the GPU; rp_plan_block_jacobi)."""
+        nb = C.c_int64()
+        _check(rp_plan_block_jacobi(self._h, int(block_size), C.byref(nb), None, None, None), "rp_plan_block_jacobi")
+        P = block_size * (block_size + 1) // 2
+        start = np.zeros(nb.value + 1, np.int32)
+        m64 = np.zeros(max(nb.value * P, 1), np.float64)
+        m32 = np.zeros(max(nb.value * P, 1), np.float32)
+        _check(rp_plan_block_jacobi(self._h, int(block_size), C.byref(nb), _ptr(start), _ptr(m64), _ptr(m32)),
+               "rp_plan_block_jacobi")
+        return start, m64[:nb.value * P], m32[:nb.value * P]
 
     def set_vec_grid(self, blocks: int):
         """Fix the solvers' elementwise-kernel grid (0 = default sizing)."""

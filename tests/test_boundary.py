@@ -69,6 +69,11 @@ int main(void) {
   F(rp_solve_opts, precision);
   F(rp_solve_opts, max_outer); F(rp_solve_opts, check_every); F(rp_solve_opts, x0_zero);
   F(rp_solve_opts, max_restarts); F(rp_solve_opts, method); F(rp_solve_opts, transpose); F(rp_solve_opts, graph);
+  F(rp_solve_opts, precond); F(rp_solve_opts, block_size);
+  printf("rp_device_ptrs %zu\n", sizeof(rp_device_ptrs));
+  F(rp_device_ptrs, row_ptr); F(rp_device_ptrs, col); F(rp_device_ptrs, perm); F(rp_device_ptrs, nl_row_ptr);
+  F(rp_device_ptrs, nl_col); F(rp_device_ptrs, val64); F(rp_device_ptrs, val32); F(rp_device_ptrs, dinv64);
+  F(rp_device_ptrs, dinv32); F(rp_device_ptrs, recv);
   F(rp_solve_info, status); F(rp_solve_info, iters); F(rp_solve_info, outer_iters); F(rp_solve_info, restarts);
   F(rp_solve_info, rel_res);
   F(rp_spmv_format, enabled); F(rp_spmv_format, reserved); F(rp_spmv_format, n_groups);
@@ -85,7 +90,8 @@ int main(void) {
         out = subprocess.check_output([exe], text=True).split("\n")
     got = dict(line.rsplit(" ", 1) for line in out if line)
     for name, cls in (("rp_rank_desc", rp.rp_rank_desc), ("rp_solve_opts", rp.rp_solve_opts),
-                      ("rp_solve_info", rp.rp_solve_info), ("rp_spmv_format", rp.rp_spmv_format)):
+                      ("rp_solve_info", rp.rp_solve_info), ("rp_spmv_format", rp.rp_spmv_format),
+                      ("rp_device_ptrs", rp.rp_device_ptrs)):
         assert int(got[name]) == ctypes.sizeof(cls), name
         for field, _ in cls._fields_:
             assert int(got[f"{name}.{field}"]) == getattr(cls, field).offset, (name, field)
@@ -96,6 +102,7 @@ def test_opts_defaults(lib_path):
     o = rp.default_opts()
     assert o.tol == 1e-8 and o.inner_tol == 1e-4 and o.precision == rp.RP_FP64 and o.check_every > 0
     assert o.update_delta == 0.1 and o.max_outer > 0 and o.method == rp.RP_CG and o.transpose == 0 and o.graph == 0
+    assert o.precond == rp.RP_PRECOND_JACOBI and o.block_size == 4
 
 
 def test_missing_library_fails_loudly():

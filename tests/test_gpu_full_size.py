@@ -130,7 +130,9 @@ def test_c3_fp64_and_mixed():
     b = w.rhs()
     _against_reference("c3", plan, m, val64, b,
                        [("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed")),
-                        ("mixed_rr", dict(precision="mixed_rr"))])
+                        ("mixed_rr", dict(precision="mixed_rr")),
+                        ("fp64 block-Jacobi 4", dict(precision="fp64", precond="block_jacobi", block_size=4)),
+                        ("mixed block-Jacobi 4", dict(precision="mixed", precond="block_jacobi", block_size=4))])
     # the same plan refreshed with non-symmetric momentum-type values:
     # update bit-exact, BiCGStab to a true residual of 1e-8
     del val64
@@ -239,7 +241,9 @@ def test_c5_solves_against_reference(order):
     vals = share_values(w, 0)
     want = oracle.update(m, oracle.receive_buffer(vals))
     update(plan, vals)
-    _against_reference("c5", plan, m, want[0], w.rhs(),
-                       [("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed")),
-                        ("mixed_rr", dict(precision="mixed_rr"))])
+    runs = [("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed")),
+            ("mixed_rr", dict(precision="mixed_rr"))]
+    if order == "fused":
+        runs.append(("fp64 block-Jacobi 4", dict(precision="fp64", precond="block_jacobi", block_size=4)))
+    _against_reference("c5", plan, m, want[0], w.rhs(), runs)
     plan.close()

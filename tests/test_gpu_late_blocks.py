@@ -29,7 +29,7 @@ def c4():
 
 
 @pytest.mark.timeout(300)
-@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_rr"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_rr", "fp64_bj"])
 def test_cg_with_late_blocks(c4, precision):
     w, m = c4
     vals = share_values(w)
@@ -37,12 +37,17 @@ def test_cg_with_late_blocks(c4, precision):
     plan = make_plan(w)
     update(plan, vals)
     b = w.rhs()
-    x_or, st, it_or, rs_or, _ = oracle.pcg(m, val64, b, tol=1e-8)
+    kw = dict(precision=precision)
+    if precision == "fp64_bj":
+        kw = dict(precision="fp64", precond="block_jacobi", block_size=4)
+        x_or, st, it_or, rs_or, _ = oracle.pcg_block_jacobi(m, val64, b, w.part.n_cells, 4, tol=1e-8)
+    else:
+        x_or, st, it_or, rs_or, _ = oracle.pcg(m, val64, b, tol=1e-8)
     assert st == 0 and rs_or == 0
-    ref, ref_info = plan.solve(dev_tensor(b), tol=1e-8, precision=precision)
+    ref, ref_info = plan.solve(dev_tensor(b), tol=1e-8, **kw)
     plan.set_vec_grid(LATE_GRID)
     for graph in (0, 1):
-        x, info = plan.solve(dev_tensor(b), tol=1e-8, precision=precision, graph=graph)
+        x, info = plan.solve(dev_tensor(b), tol=1e-8, graph=graph, **kw)
         xh = x.cpu().numpy()
         rr = oracle.true_relres(m, val64, b, xh)
         err = np.linalg.norm(xh - x_or) / np.linalg.norm(x_or)
@@ -50,7 +55,7 @@ def test_cg_with_late_blocks(c4, precision):
               f"{ref_info['iters']}), restarts {info['restarts']}, rel.res {rr:.2e}, err {err:.2e}")
         assert info["status"] == 0 and info["restarts"] == 0, info
         assert rr <= 1e-8 and err <= 1e-6, (rr, err)
-        if precision == "fp64":
+        if precision.startswith("fp64"):
             assert abs(info["iters"] - it_or) <= max(3, int(0.02 * it_or)), (info["iters"], it_or)
     plan.set_vec_grid(0)
     plan.close()
