@@ -273,6 +273,22 @@ int rp_update_values(rp_plan* plan, const double* const* diag, const double* con
  * ranks write straight into when they can reach device memory). */
 int rp_update_values_slots(rp_plan* plan, const double* slots, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * update as rp_update_values with every per-rank array in device memory,
+ * same results bit for bit.  Its only scratch, the table of 4 pointers per
+ * rank that the reorder reads, lives in a fixed library-owned device array
+ * of 4 * RP_NOALLOC_MAX_RANKS pointers (128 KiB on each GPU the library runs
+ * on, held until the process ends) instead of plan memory, and the call
+ * makes no hipMalloc or hipFree.  RP_ERR_ARG for a share of more than
+ * RP_NOALLOC_MAX_RANKS ranks or an array that is not device memory (checked
+ * before any device work).  Every call on one GPU shares that array: calls
+ * that overlap on one GPU (other streams, threads or plans) race, so the
+ * caller serialises them. */
+#define RP_NOALLOC_MAX_RANKS 4096
+int rp_update_values_noalloc(rp_plan* plan, const double* const* diag, const double* const* upper,
+                             const double* const* lower, const double* const* iface, void* stream);
+
 
 /* ---- kernels on the fused matrix ---------------------------------------- *
  * y = A x over the local block, x and y device arrays of n_rows elements:

@@ -48,7 +48,8 @@ EXPORTED = ["rp_plan_create", "rp_plan_destroy", "rp_plan_sizes", "rp_plan_get_c
             "rp_update_values", "rp_update_values_slots", "rp_spmv", "rp_solve", "rp_solve_opts_default",
             "rp_value_grad", "rp_sync", "rp_last_error", "rp_plan_set_timing", "rp_plan_kernel_stats",
             "rp_plan_set_solve_order", "rp_plan_solve_order", "rp_rcm_order", "rp_plan_device_ptrs",
-            "rp_plan_set_vec_grid", "rp_plan_block_jacobi"]
+            "rp_plan_set_vec_grid", "rp_update_values_noalloc", "rp_plan_block_jacobi"]
+RP_NOALLOC_MAX_RANKS = 4096
 RP_PRECOND_JACOBI, RP_PRECOND_BLOCK_JACOBI = 0, 1
 RP_BJ_MAX_BLOCK = 8
 
@@ -112,6 +113,7 @@ _sig = {
     "rp_plan_set_spmv_format": (C.c_int, [_P, C.c_int32]),
     "rp_update_values": (C.c_int, [_P, _PP, _PP, _PP, _PP, _P]),
     "rp_update_values_slots": (C.c_int, [_P, _P, _P]),
+    "rp_update_values_noalloc": (C.c_int, [_P, _PP, _PP, _PP, _PP, _P]),
     "rp_spmv": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
     "rp_solve": (C.c_int, [_P, _P, _P, C.POINTER(rp_solve_opts), C.POINTER(rp_solve_info), _P]),
     "rp_solve_opts_default": (None, [C.POINTER(rp_solve_opts)]),
@@ -370,6 +372,26 @@ class Plan:
         if host:
             # host arrays may be released by the caller on return
             self.sync()
+        self.version += 1
+
+    def update_noalloc(self, diag, upper, iface, lower=None, stream=None):
+        """rp_update_values_noalloc: per-rank float64 CUDA tensors; the library
+        allocates nothing for the call (its pointer table lives in a fixed
+        device array shared by all calls on the GPU)."""
+        A = self.alpha
+
+        def table(lst):
+            assert len(lst) == A, "one array per rank of the share"
+            t = (C.c_void_p * A)()
+            for i, a in enumerate(lst):
+                t[i] = _ptr(a).value
+            return t
+
+        td, tu, ti = table(diag), table(upper), table(iface)
+        tl = table(lower) if lower is not None else None
+        _check(rp_update_values_noalloc(self._h, C.cast(td, _PP), C.cast(tu, _PP),
+                                        C.cast(tl, _PP) if tl else None, C.cast(ti, _PP), _stream_handle(stream)),
+               "rp_update_values_noalloc")
         self.version += 1
 
     def update_slots(self, slots, stream=None):
