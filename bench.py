@@ -59,6 +59,10 @@ def parse():
                          "(minutes of host time at 256^3)")
     ap.add_argument("--solve-order", default="fused", choices=["fused", "rcm"],
                     help="row order CG and the mixed solvers run in (rcm: the plan's reverse Cuthill-McKee copy)")
+    ap.add_argument("--no-preconditioners", action="store_true",
+                    help="skip the Jacobi vs block-Jacobi leg (shorter profiler runs)")
+    ap.add_argument("--rank-procs", type=int, default=8,
+                    help="rank processes for the multi-process update leg (0: skip it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 2 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -100,12 +104,7 @@ def main():
               "splitting the ranks over several GPUs is described, not implemented", file=sys.stderr)
         sys.exit(2)
 
-    import torch
     import synth
-    from paper_2510_08536_amd import Plan, default_opts, RP_KERNEL_SPMV64, RP_KERNEL_SPMV32, RP_KERNEL_SCATTER
-
-    assert torch.cuda.is_available()
-    dev = torch.device("cuda:0")
     n_steps_total = a.warmup + a.steps
     t0 = time.time()
     w = synth.build(a.config, timesteps=max(n_steps_total, 1))
@@ -113,6 +112,26 @@ def main():
     p = w.part
     ranks = [p.rank(r) for r in range(w.n_ranks)]
     print(f"[bench] {a.config}: {w.n_cells} cells, {w.n_ranks} ranks, generated in {gen_s:.1f}s", flush=True)
+
+    # rank processes, started before this process touches the GPU
+    layout, so = [], 0
+    for r in range(w.n_ranks):
+        nc, nf, ni = int(p.n_cells[r]), len(ranks[r]["owner"]), len(ranks[r]["iface_cell"])
+        layout.append((so, nc, nf, ni))
+        so += nc + 2 * nf + ni
+    pool, pool_err = None, None
+    if a.rank_procs > 0:
+        try:
+            from paper_2510_08536_amd.ranks import RankPool
+            pool = RankPool(min(a.rank_procs, w.n_ranks), layout)
+        except Exception as e:  # reported in the JSON line, the rest still runs
+            pool_err = f"{type(e).__name__}: {e}"
+
+    import torch
+    from paper_2510_08536_amd import Plan, default_opts, RP_KERNEL_SPMV64, RP_KERNEL_SPMV32, RP_KERNEL_SCATTER
+
+    assert torch.cuda.is_available()
+    dev = torch.device("cuda:0")
 
     # ---- plan (once) -------------------------------------------------------
     torch.cuda.synchronize()
@@ -241,6 +260,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n_spmv, ms_spmv = plan.kernel_stats(RP_KERNEL_SPMV64)
+    ranks_update = rank_process_update(pool, pool_err, plan, w, layout, torch) if a.rank_procs > 0 else None
 
     # SpMV alone: 200 launches of y = A x on the last step's pressure matrix
     plan.update(*steps_vals[n_steps_total - 1])
@@ -262,10 +282,14 @@ def main():
     # block-Jacobi preconditioner (blocks of consecutive rows inside a rank)
     # against Jacobi on the same system: 3 timed solves each, after one warm-up
     bj = {}
-    for label, kw in (("jacobi", dict(precision="fp64")),
-                      ("block_jacobi_4", dict(precision="fp64", precond="block_jacobi", block_size=4)),
-                      ("block_jacobi_8", dict(precision="fp64", precond="block_jacobi", block_size=8)),
-                      ("mixed_block_jacobi_4", dict(precision="mixed", precond="block_jacobi", block_size=4))):
+    legs = () if a.no_preconditioners else (("jacobi", dict(precision="fp64")),
+                                            ("block_jacobi_4", dict(precision="fp64", precond="block_jacobi",
+                                                                    block_size=4)),
+                                            ("block_jacobi_8", dict(precision="fp64", precond="block_jacobi",
+                                                                    block_size=8)),
+                                            ("mixed_block_jacobi_4", dict(precision="mixed", precond="block_jacobi",
+                                                                          block_size=4)))
+    for label, kw in legs:
         plan.solve(b, opts=default_opts(tol=1e-8, x0_zero=1, **kw))
         ts, its = [], []
         for _ in range(3):
@@ -377,6 +401,7 @@ def main():
         "update_ms": round(med(upd), 3),
         "update_scatter_ms": round(ms_scat / max(n_scat, 1), 4),
         "update_host_staged_ms": round(update_host_ms, 3),
+        "update_from_rank_processes": ranks_update,
         "plan_ms": round(plan_ms, 1),
         "solve_order_build_ms": None if order_ms is None else round(order_ms, 1),
         "spmv_GBps": round(spmv_gbs, 1),
@@ -407,6 +432,72 @@ def main():
                                            answers["fp64"][1]["iters"])
     print(json.dumps(out), flush=True)
     plan.close()
+
+
+def rank_process_update(pool, pool_err, plan, w, layout, torch):
+    """The update with the ranks' values in other processes (timesteps 0-2,
+    each twice, the second timed): every process writes its ranks' slot
+    blocks into the plan's device receive buffer through its IPC handle and
+    the plan reorders that buffer (GPU-aware path), or writes them into a
+    shared host buffer that rp_update_values copies to the device, one copy
+    per rank array (host-buffer path).  Wall time from the request to the
+    reordered matrix."""
+    if pool is None:
+        return {"error": pool_err or "no rank processes"}
+    try:
+        T = min(3, len(w.step_seqs))
+        bufs = []
+        for t in range(T):
+            v = w.values(t)
+            parts = []
+            for r, (off, nc, nf, ni) in enumerate(layout):
+                c0, f0, i0 = w.part.cell_ptr[r], w.part.face_ptr[r], w.part.if_ptr[r]
+                up = v.upper[f0:f0 + nf]
+                parts += [v.diag[c0:c0 + nc], up, up, v.iface[i0:i0 + ni]]
+            bufs.append(np.concatenate(parts))
+            del v, parts
+        t0 = time.perf_counter()
+        pool.load(bufs)
+        load_s = time.perf_counter() - t0
+        del bufs
+        pool.attach_device(plan.export_recv())
+        host = pool.host_buffer(plan.n_slots)
+        views = [host[off:off + nc + 2 * nf + ni] for off, nc, nf, ni in layout]
+        hd = [vw[:nc] for vw, (_, nc, nf, ni) in zip(views, layout)]
+        hu = [vw[nc:nc + nf] for vw, (_, nc, nf, ni) in zip(views, layout)]
+        hl = [vw[nc + nf:nc + 2 * nf] for vw, (_, nc, nf, ni) in zip(views, layout)]
+        hi = [vw[nc + 2 * nf:] for vw, (_, nc, nf, ni) in zip(views, layout)]
+        dev_ms, host_ms, dev_w, host_w = [], [], [], []
+        for rep in range(2):
+            for t in range(T):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ww = pool.write_device(t)
+                plan.update_from_recv()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                wh = pool.write_host(t)
+                plan.update(hd, hu, hi, lower=hl)      # host arrays: copies + reorder, synchronised
+                t2 = time.perf_counter()
+                if rep == 1:
+                    dev_ms.append(1e3 * (t1 - t0))
+                    host_ms.append(1e3 * (t2 - t1))
+                    dev_w.append(1e3 * ww)
+                    host_w.append(1e3 * wh)
+        out = {"processes": len(pool.procs), "ranks": len(layout),
+               "gpu_aware_ipc_ms": round(float(np.median(dev_ms)), 3),
+               "gpu_aware_ipc_worker_write_ms": round(float(np.median(dev_w)), 3),
+               "host_buffer_ms": round(float(np.median(host_ms)), 3),
+               "host_buffer_worker_write_ms": round(float(np.median(host_w)), 3),
+               "speedup_ipc_vs_host": round(float(np.median(host_ms)) / float(np.median(dev_ms)), 3),
+               "values_load_s": round(load_s, 2),
+               "note": "wall time from the request to the reordered matrix, median of 3 timesteps; values "
+                       "start in each rank process's own (pageable) memory"}
+    except Exception as e:
+        out = {"error": f"{type(e).__name__}: {e}"}
+    finally:
+        pool.close()
+    return out
 
 
 def accuracy(w, config, answers):

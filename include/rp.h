@@ -167,8 +167,7 @@ int rp_plan_get_csr(rp_plan* plan, int32_t* row_ptr, int32_t* col, int32_t* perm
 /* Device pointers to the plan's pattern and current values, valid until
  * rp_plan_destroy and read-only for the caller.  The arrays keep the layouts
  * of rp_plan_get_csr and rp_plan_get_values; the values change with every
- * update, so read them in stream order after it.  recv is the receive buffer
- * in slot order (the update's staging area).  No device work, no sync. */
+ * update, so read them in stream order after it.  No device work, no sync. */
 typedef struct rp_device_ptrs {
     const int32_t* row_ptr;     /* [n_rows+1] fused local block */
     const int32_t* col;         /* [nnz_local] local column ids, ascending per row */
@@ -289,6 +288,32 @@ int rp_update_values_slots(rp_plan* plan, const double* slots, void* stream);
 int rp_update_values_noalloc(rp_plan* plan, const double* const* diag, const double* const* upper,
                              const double* const* lower, const double* const* iface, void* stream);
 
+/* ---- ranks in other processes (Sec. 3 update procedure; the GPU-aware
+ * communication study of Sec. 4) -------------------------------------------- *
+ * The owner exports its plan's receive buffer (device memory, n_slots
+ * doubles) as an IPC handle; a rank process attaches it and writes its own
+ * slot block [diag | upper | lower | interface] at its offset of U
+ * (rp_plan_sizes' slot_off) straight into the owner's device memory, the
+ * one-GPU analogue of a rank sending with GPU-aware MPI.  When every rank
+ * has returned from rp_recv_write, the owner reorders the buffer with
+ * rp_update_values_slots(plan, recv, stream), recv from
+ * rp_plan_device_ptrs.  Ranks write disjoint slot ranges; the owner must not
+ * update from the buffer while writes are in progress. */
+typedef struct rp_ipc_handle {
+    char bytes[64];            /* opaque; hipIpcMemHandle_t of the receive buffer */
+} rp_ipc_handle;
+/* Owner side.  RP_ERR_UNSUPPORTED for a buffer of 2 GiB or more. */
+int rp_plan_export_recv(rp_plan* plan, rp_ipc_handle* out, int64_t* n_slots);
+/* Rank side (another process, same GPU current): map the owner's buffer;
+ * *recv is a device pointer into it, valid until rp_recv_detach. */
+int rp_recv_attach(const rp_ipc_handle* handle, double** recv);
+/* Copy one rank's values (host or device memory; lower NULL = symmetric, the
+ * lower region gets upper) to recv[slot_offset ...] in its LDU order.
+ * Returns when the values are in the owner's device memory. */
+int rp_recv_write(double* recv, int64_t slot_offset, const double* diag, int32_t n_cells,
+                  const double* upper, int32_t n_faces, const double* lower, const double* iface,
+                  int32_t n_iface, void* stream);
+int rp_recv_detach(double* recv);
 
 /* ---- kernels on the fused matrix ---------------------------------------- *
  * y = A x over the local block, x and y device arrays of n_rows elements:

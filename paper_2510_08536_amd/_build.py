@@ -17,15 +17,15 @@ LIB = os.path.join(HERE, "librp.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["plan.hip", "update.hip", "spmv.hip", "cg.hip", "grad.hip", "order.hip", "precond.hip", "noalloc.hip", "capi.cpp"]
+SOURCES = ["plan.hip", "update.hip", "spmv.hip", "cg.hip", "grad.hip", "order.hip", "precond.hip", "noalloc.hip", "capi.cpp", "ipc.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I", INCLUDE]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, out_dir: str = BUILD, extra=()) -> str:
+    obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     p = subprocess.run(cmd, capture_output=True, text=True)
@@ -52,6 +52,19 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print("built", LIB)
     return LIB
+
+
+def build_variant(out_dir: str, extra_flags=(), link_flags=()) -> str:
+    """The same library built into out_dir with extra compile and link flags
+    (for instance host-side sanitizers); returns the path of the .so."""
+    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
+        objs = list(ex.map(lambda src: _compile(src, out_dir, extra_flags), SOURCES))
+    lib = os.path.join(out_dir, "librp_variant.so")
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *link_flags, "-o", lib, *objs]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError(f"link failed:\n{p.stderr}")
+    return lib
 
 
 if __name__ == "__main__":

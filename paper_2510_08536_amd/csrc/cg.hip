@@ -479,6 +479,126 @@ cg_precond_bj(int32_t nb, const int32_t* __restrict__ start, const T* __restrict
     if (threadIdx.x == 0) part[PART_RZ + blockIdx.x] = b1;
 }
 
+// Lane-per-row forms for aligned blocks: every block starts at a multiple of
+// BS (each rank's rows a multiple of BS) and BS divides 64, so a block's rows
+// are BS neighbouring lanes of one wavefront.  Loads and stores are then
+// coalesced like the Jacobi kernels'; a lane takes its block's residuals
+// from its neighbours with shuffles and reads its own row of the packed
+// inverse.  Same products and sums, in the same order, as the per-block
+// form.
+template <typename T, int BS>
+__device__ __forceinline__ T bj_lane_solve(T ri, int32_t i, const T* __restrict__ minv) {
+#pragma clang fp contract(off)
+    constexpr int P = BS * (BS + 1) / 2;
+    const int lane = threadIdx.x & 63;
+    const int li = lane & (BS - 1);        // the row's place in its block
+    const int l0 = lane - li;
+    const T* mb = minv + (int64_t)(i / BS) * P;
+    T mrow[BS];
+#pragma unroll
+    for (int j = 0; j < BS; ++j) {
+        const int a = li < j ? li : j, c = li < j ? j : li;
+        mrow[j] = mb[a * BS - a * (a - 1) / 2 + (c - a)];
+    }
+    T zi = T(0);
+#pragma unroll
+    for (int j = 0; j < BS; ++j) zi += mrow[j] * __shfl(ri, l0 + j, 64);
+    return zi;
+}
+
+template <typename T, int BS>
+__global__ void __launch_bounds__(VEC_BLOCK)
+cg_update_r_bj_lane(int32_t n, int32_t k_arg, int32_t g_spmv, const T* __restrict__ minv, T* __restrict__ r,
+                    const T* __restrict__ q, T* __restrict__ z, T* __restrict__ part, CgState<T>* st) {
+#pragma clang fp contract(off)
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (st->done != CG_RUNNING) {
+        if (lead) st->kk = -1;
+        return;
+    }
+    const int32_t k = k_arg >= 0 ? k_arg : st->iter;
+    if (k >= st->max_iter) {
+        if (lead) st->kk = -1;
+        return;
+    }
+    __shared__ T red[VEC_BLOCK / 64];
+    const T pq = sum_partials_all<T, VEC_BLOCK>(part + PART_A, g_spmv, red);
+    if (!(pq > T(0)) || !isfinite(pq)) {
+        if (lead) {
+            st->pq = pq;
+            st->iter = k;
+            st->kk = -1;
+            st->done = CG_BREAKDOWN;
+        }
+        return;
+    }
+    const T a = st->rz[k & 3] / pq;
+    T prz = T(0), prr = T(0);
+    // whole wavefronts per trip (the grid stride is a multiple of 64), so a
+    // block's lanes are active together; rows past n carry 0
+    const int32_t di = gridDim.x * VEC_BLOCK;
+    for (int32_t base = blockIdx.x * VEC_BLOCK; base < n; base += di) {
+        const int32_t i = base + threadIdx.x;
+        const bool in = i < n;
+        const T ri = in ? r[i] - a * q[i] : T(0);
+        const T zi = bj_lane_solve<T, BS>(ri, in ? i : 0, minv);
+        if (in) {
+            r[i] = ri;
+            z[i] = zi;
+            prz += ri * zi;
+            prr += ri * ri;
+        }
+    }
+    const T b1 = block_sum<T, VEC_BLOCK>(prz, red);
+    const T b2 = block_sum<T, VEC_BLOCK>(prr, red);
+    if (threadIdx.x == 0) {
+        part[PART_RZ + blockIdx.x] = b1;
+        part[PART_RR + blockIdx.x] = b2;
+    }
+    if (lead) {
+        st->pq = pq;
+        st->alpha = a;
+        st->kk = k;
+    }
+}
+
+template <typename T, int BS, bool RZ_RR>
+__global__ void __launch_bounds__(VEC_BLOCK)
+cg_precond_bj_lane(int32_t n, const T* __restrict__ minv, const T* __restrict__ r, T* __restrict__ out,
+                   T* __restrict__ part) {
+#pragma clang fp contract(off)
+    __shared__ T red[VEC_BLOCK / 64];
+    T prz = T(0), prr = T(0);
+    const int32_t di = gridDim.x * VEC_BLOCK;
+    for (int32_t base = blockIdx.x * VEC_BLOCK; base < n; base += di) {
+        const int32_t i = base + threadIdx.x;
+        const bool in = i < n;
+        const T ri = in ? r[i] : T(0);
+        const T zi = bj_lane_solve<T, BS>(ri, in ? i : 0, minv);
+        if (in) {
+            out[i] = zi;
+            prz += ri * zi;
+            prr += ri * ri;
+        }
+    }
+    const T b1 = block_sum<T, VEC_BLOCK>(prz, red);
+    if (RZ_RR) {
+        const T b2 = block_sum<T, VEC_BLOCK>(prr, red);
+        if (threadIdx.x == 0) part[PART_RR + blockIdx.x] = b2;
+    }
+    if (threadIdx.x == 0) part[PART_RZ + blockIdx.x] = b1;
+}
+
+#define RP_DISPATCH_BS_LANE(bs, CALL) \
+    do {                              \
+        switch (bs) {                 \
+        case 1: CALL(1); break;       \
+        case 2: CALL(2); break;       \
+        case 4: CALL(4); break;       \
+        default: CALL(8); break;      \
+        }                             \
+    } while (0)
+
 #define RP_DISPATCH_BS(bs, CALL) \
     do {                         \
         switch (bs) {            \
@@ -525,6 +645,7 @@ struct Cg {
     const T* bj_minv = nullptr;
     int32_t bj_nb = 0;
     int32_t bj_bs = 0;
+    bool bj_lane = false;   // aligned blocks: the lane-per-row kernels
     T* z = nullptr;
 };
 
@@ -584,7 +705,13 @@ int launch_finalize(Cg<T>& c, int32_t mode, int32_t k, T tol2, T pause_frac2, in
 // partials are still in PART_A / PART_B)
 template <typename T>
 int launch_start(Cg<T>& c, int32_t k, T tol2, T pause_frac2, int32_t max_iter) {
-    if (c.bj_minv) {
+    if (c.bj_minv && c.bj_lane) {
+#define RP_LAUNCH(BS)                                                                                          \
+    hipLaunchKernelGGL((cg_precond_bj_lane<T, BS, false>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, c.bj_minv, \
+                       c.r, c.p, c.part)
+        RP_DISPATCH_BS_LANE(c.bj_bs, RP_LAUNCH);
+#undef RP_LAUNCH
+    } else if (c.bj_minv) {
 #define RP_LAUNCH(BS)                                                                                          \
     hipLaunchKernelGGL((cg_precond_bj<T, BS, false>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.bj_nb, c.bj_start, \
                        c.bj_minv, c.r, c.p, c.part)
@@ -602,11 +729,19 @@ template <typename T>
 int launch_resume(Cg<T>& c) {
     const int32_t k = c.h->iter - 1;
     if (c.bj_minv) {
+        if (c.bj_lane) {
+#define RP_LAUNCH(BS)                                                                                         \
+    hipLaunchKernelGGL((cg_precond_bj_lane<T, BS, true>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, c.bj_minv, \
+                       c.r, c.z, c.part)
+            RP_DISPATCH_BS_LANE(c.bj_bs, RP_LAUNCH);
+#undef RP_LAUNCH
+        } else {
 #define RP_LAUNCH(BS)                                                                                         \
     hipLaunchKernelGGL((cg_precond_bj<T, BS, true>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.bj_nb, c.bj_start, \
                        c.bj_minv, c.r, c.z, c.part)
-        RP_DISPATCH_BS(c.bj_bs, RP_LAUNCH);
+            RP_DISPATCH_BS(c.bj_bs, RP_LAUNCH);
 #undef RP_LAUNCH
+        }
         hipLaunchKernelGGL((cg_update_xp<T, true>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, k, c.g_vec, 1, c.r,
                            c.dinv, c.z, c.x, c.p, c.part, c.st);
     } else {
@@ -630,11 +765,19 @@ int launch_iteration(Cg<T>& c, int32_t k, hipStream_t s) {
 #undef RP_LAUNCH
     RP_TRY(timing_end(c.plan, c.kernel_id, s));
     if (c.bj_minv) {
+        if (c.bj_lane) {
+#define RP_LAUNCH(BS)                                                                                              \
+    hipLaunchKernelGGL((cg_update_r_bj_lane<T, BS>), gv, bv, 0, s, c.n, k, c.g_spmv, c.bj_minv, c.r, c.q, c.z, c.part, \
+                       c.st)
+            RP_DISPATCH_BS_LANE(c.bj_bs, RP_LAUNCH);
+#undef RP_LAUNCH
+        } else {
 #define RP_LAUNCH(BS)                                                                                          \
     hipLaunchKernelGGL((cg_update_r_bj<T, BS>), gv, bv, 0, s, c.n, k, c.g_spmv, c.bj_nb, c.bj_start, c.bj_minv, \
                        c.r, c.q, c.z, c.part, c.st)
-        RP_DISPATCH_BS(c.bj_bs, RP_LAUNCH);
+            RP_DISPATCH_BS(c.bj_bs, RP_LAUNCH);
 #undef RP_LAUNCH
+        }
         hipLaunchKernelGGL((cg_update_xp<T, true>), gv, bv, 0, s, c.n, k, c.g_vec, 0, c.r, c.dinv, c.z, c.x, c.p,
                            c.part, c.st);
     } else {
@@ -662,7 +805,8 @@ int cg_graph(Cg<T>& c, int chunk, hipGraphExec_t* out) {
                               (uint64_t)c.g_spmv,       (uint64_t)c.g_vec,      (uint64_t)(uint32_t)c.xw_mode,
                               (uint64_t)(uint32_t)c.w.d[0], (uint64_t)(uint32_t)c.w.d[1],
                               (uint64_t)(uintptr_t)c.bj_minv, (uint64_t)(uintptr_t)c.bj_start,
-                              (uint64_t)(uintptr_t)c.z, ((uint64_t)(uint32_t)c.bj_nb << 8) | (uint32_t)c.bj_bs};
+                              (uint64_t)(uintptr_t)c.z,
+                              ((uint64_t)(uint32_t)c.bj_nb << 16) | ((uint32_t)c.bj_lane << 8) | (uint32_t)c.bj_bs};
     if (g.exec && std::memcmp(g.key, key, sizeof key) == 0) {
         *out = g.exec;
         return RP_OK;
@@ -721,6 +865,7 @@ void use_block_jacobi(Cg<T>& c, const rp_plan* p, const T* minv, T* z) {
     c.bj_minv = minv;
     c.bj_nb = (int32_t)p->bj_blocks;
     c.bj_bs = p->bj_bs;
+    c.bj_lane = p->bj_aligned;
     c.z = z;
 }
 

@@ -115,6 +115,9 @@ int bj_prepare(rp_plan* p, int32_t bs, hipStream_t s) {
         p->bj_blocks = nb;
         p->bj_bs = bs;
         p->bj_version = -1;
+        bool aligned = 64 % bs == 0 && (bs & (bs - 1)) == 0;
+        for (int32_t c : p->n_cells) aligned = aligned && c % bs == 0;
+        p->bj_aligned = aligned;
     }
     if (!p->d_z) {
         RP_HIP_TRY(hipMalloc(&p->d_z, sizeof(double) * (size_t)std::max<int64_t>(p->n_rows, 1)));

@@ -224,6 +224,7 @@ struct rp_plan {
     // block-Jacobi preconditioner (precond.hip), built on first use for a
     // block size and rebuilt after every update
     int32_t bj_bs = 0;                 // block size of the tables below (0: none)
+    bool bj_aligned = false;           // every block starts at a multiple of bs, and bs divides 64
     int64_t bj_blocks = 0;
     int64_t bj_version = -1;           // values_version the inverses were built from
     int32_t* d_bj_start = nullptr;     // [bj_blocks + 1] first fused row of each block

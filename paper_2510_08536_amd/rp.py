@@ -48,10 +48,11 @@ EXPORTED = ["rp_plan_create", "rp_plan_destroy", "rp_plan_sizes", "rp_plan_get_c
             "rp_update_values", "rp_update_values_slots", "rp_spmv", "rp_solve", "rp_solve_opts_default",
             "rp_value_grad", "rp_sync", "rp_last_error", "rp_plan_set_timing", "rp_plan_kernel_stats",
             "rp_plan_set_solve_order", "rp_plan_solve_order", "rp_rcm_order", "rp_plan_device_ptrs",
-            "rp_plan_set_vec_grid", "rp_update_values_noalloc", "rp_plan_block_jacobi"]
-RP_NOALLOC_MAX_RANKS = 4096
+            "rp_plan_set_vec_grid", "rp_update_values_noalloc", "rp_plan_block_jacobi", "rp_plan_export_recv",
+            "rp_recv_attach", "rp_recv_write", "rp_recv_detach"]
 RP_PRECOND_JACOBI, RP_PRECOND_BLOCK_JACOBI = 0, 1
 RP_BJ_MAX_BLOCK = 8
+RP_NOALLOC_MAX_RANKS = 4096
 
 
 class rp_rank_desc(C.Structure):
@@ -84,6 +85,10 @@ class rp_device_ptrs(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class rp_ipc_handle(C.Structure):
+    _fields_ = [("bytes", C.c_char * 64)]
 
 
 class rp_spmv_format(C.Structure):
@@ -128,6 +133,10 @@ _sig = {
     "rp_plan_device_ptrs": (C.c_int, [_P, C.POINTER(rp_device_ptrs)]),
     "rp_plan_set_vec_grid": (C.c_int, [_P, C.c_int32]),
     "rp_plan_block_jacobi": (C.c_int, [_P, C.c_int32, _i64p, _P, _P, _P]),
+    "rp_plan_export_recv": (C.c_int, [_P, C.POINTER(rp_ipc_handle), _i64p]),
+    "rp_recv_attach": (C.c_int, [C.POINTER(rp_ipc_handle), C.POINTER(C.c_void_p)]),
+    "rp_recv_write": (C.c_int, [_P, C.c_int64, _P, C.c_int32, _P, C.c_int32, _P, _P, C.c_int32, _P]),
+    "rp_recv_detach": (C.c_int, [_P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -394,6 +403,19 @@ class Plan:
                "rp_update_values_noalloc")
         self.version += 1
 
+    def export_recv(self) -> bytes:
+        """IPC handle (64 bytes) of the plan's receive buffer, for rank
+        processes that write their values straight into it (RecvWriter)."""
+        h = rp_ipc_handle()
+        _check(rp_plan_export_recv(self._h, C.byref(h), None), "rp_plan_export_recv")
+        return C.string_at(C.addressof(h), 64)
+
+    def update_from_recv(self, stream=None):
+        """Reorder the plan's own receive buffer (filled by rank processes)."""
+        _check(rp_update_values_slots(self._h, C.c_void_p(self.device_ptrs()["recv"]), _stream_handle(stream)),
+               "rp_update_values_slots")
+        self.version += 1
+
     def update_slots(self, slots, stream=None):
         """slots: float64 CUDA tensor of n_slots values in receive-buffer order."""
         assert slots.is_cuda and slots.dtype == _torch().float64 and slots.is_contiguous()
@@ -449,3 +471,30 @@ class Plan:
         n, ms = C.c_int64(), C.c_double()
         _check(rp_plan_kernel_stats(self._h, kernel, C.byref(n), C.byref(ms)), "rp_plan_kernel_stats")
         return n.value, ms.value
+
+
+class RecvWriter:
+    """Rank-process side of the receive buffer: maps the owner's buffer from
+    its IPC handle and writes one rank's slot block at a time into it."""
+
+    def __init__(self, handle: bytes):
+        h = rp_ipc_handle()
+        C.memmove(C.addressof(h), handle, 64)
+        ptr = C.c_void_p()
+        _check(rp_recv_attach(C.byref(h), C.byref(ptr)), "rp_recv_attach")
+        self._ptr = ptr
+
+    def write(self, slot_offset: int, diag, upper, iface, lower=None, stream=None):
+        """Host (numpy) or device (torch) float64 arrays of one rank, LDU order."""
+        arrs = [diag, upper, iface] + ([lower] if lower is not None else [])
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) if isinstance(a, np.ndarray) else a for a in arrs]
+        d, u, i = arrs[:3]
+        lo = arrs[3] if lower is not None else None
+        _check(rp_recv_write(self._ptr, int(slot_offset), _ptr(d), len(d), _ptr(u), len(u),
+                             _ptr(lo) if lo is not None else None, _ptr(i), len(i), _stream_handle(stream)),
+               "rp_recv_write")
+
+    def close(self):
+        if getattr(self, "_ptr", None) is not None:
+            rp_recv_detach(self._ptr)
+            self._ptr = None

@@ -319,3 +319,34 @@ def test_plan_rejects_bad_addressing(mutation, code):
     with pytest.raises(RpError) as e:
         Plan(nca, first, alpha, ranks)
     assert e.value.code == code
+
+
+class _DevArray:
+    """A device array the library owns, seen by torch without a copy."""
+
+    def __init__(self, ptr, n, typestr):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, False), "version": 3}
+
+
+@pytest.mark.parametrize("name", ["slabs_c1like", "rcb_mixed", "ragged_rcb7"])
+def test_device_ptrs(name):
+    """rp_plan_device_ptrs: the device arrays hold what rp_plan_get_csr and
+    rp_plan_get_values return (pattern, P, values in CSR order, Jacobi
+    inverses), in either SpMV form."""
+    torch = torch_mod()
+    w = _work(name)
+    m, buf, val64, val32, d64, d32 = oracle_system(w)
+    plan = make_plan(w)
+    update(plan, share_values(w))
+    dev = lambda ptr, n, t: torch.as_tensor(_DevArray(ptr, n, t), device="cuda").cpu().numpy()
+    for coded in (True, False):
+        plan.set_spmv_format(coded)
+        ptrs = plan.device_ptrs()
+        assert np.array_equal(dev(ptrs["row_ptr"], m.n_rows + 1, "<i4"), m.row_ptr)
+        assert np.array_equal(dev(ptrs["col"], m.nnz_local, "<i4"), m.col)
+        assert np.array_equal(dev(ptrs["perm"], m.n_slots, "<i4"), m.perm)
+        assert_bits_equal(dev(ptrs["val64"], plan.n_slots, "<f8"), val64, f"{name} device val64")
+        assert_bits_equal(dev(ptrs["val32"], plan.n_slots, "<f4"), val32, f"{name} device val32")
+        assert_bits_equal(dev(ptrs["dinv64"], m.n_rows, "<f8"), d64, f"{name} device dinv64")
+        assert_bits_equal(dev(ptrs["dinv32"], m.n_rows, "<f4"), d32, f"{name} device dinv32")
+    plan.close()
