@@ -59,6 +59,8 @@ def parse():
                          "(minutes of host time at 256^3)")
     ap.add_argument("--solve-order", default="fused", choices=["fused", "rcm"],
                     help="row order CG and the mixed solvers run in (rcm: the plan's reverse Cuthill-McKee copy)")
+    ap.add_argument("--no-loop-legs", action="store_true",
+                    help="skip the single-launch CG loop against three-kernel iteration legs")
     ap.add_argument("--no-preconditioners", action="store_true",
                     help="skip the Jacobi vs block-Jacobi leg (shorter profiler runs)")
     ap.add_argument("--rank-procs", type=int, default=8,
@@ -304,6 +306,29 @@ def main():
     for label in bj:
         bj[label]["speedup_vs_jacobi"] = round(bj["jacobi"]["ms_per_solve"] / bj[label]["ms_per_solve"], 3)
     print(f"[bench] preconditioners: {bj}", flush=True)
+    # CG iterations in one cooperative launch against the three-kernel
+    # iteration (kernel timing off in both): per-iteration time, on systems
+    # of up to 2^20 rows
+    loop = {}
+    for prec in (() if a.no_loop_legs or n > (1 << 20) else ("fp64", "mixed")):
+        for fl, label in ((0, "three_kernel"), (1, "single_launch")):
+            kw = dict(tol=1e-8, x0_zero=1, precision=prec, fused_loop=fl)
+            plan.solve(b, opts=default_opts(**kw))
+            ts, its = [], []
+            for _ in range(3):
+                e_a = ev()
+                _, ib = plan.solve(b, opts=default_opts(**kw))
+                e_b = ev()
+                torch.cuda.synchronize()
+                assert ib["status"] == 0 and ib["rel_res"] <= 1e-8, ib
+                ts.append(e_a.elapsed_time(e_b))
+                its.append(ib["iters"])
+            ms, it_ = float(np.median(ts)), int(np.median(its))
+            loop[f"{prec}_{label}"] = {"ms_per_solve": round(ms, 3), "iters": it_,
+                                       "us_per_iter": round(1e3 * ms / max(it_, 1), 2)}
+        loop[f"{prec}_single_launch"]["speedup"] = round(loop[f"{prec}_three_kernel"]["ms_per_solve"]
+                                                         / loop[f"{prec}_single_launch"]["ms_per_solve"], 3)
+    print(f"[bench] cg loop: {loop}", flush=True)
 
     el = lambda e_a, e_b: e_a.elapsed_time(e_b)
     upd = [el(r["ev"][0], r["ev"][1]) for r in recs]
@@ -388,6 +413,9 @@ def main():
         "restarts_in_timed_solves": restarts,
         "preconditioners": dict(bj, note="last timestep's system, x0 = 0, tol 1e-8, 3 solves each (median); "
                                          "block_jacobi_b: blocks of b consecutive rows inside each rank"),
+        "cg_loop": dict(loop, note="last timestep's system, x0 = 0, tol 1e-8, 3 solves each (median); "
+                                   "single_launch: the iterations in one cooperative launch with grid-wide "
+                                   "barriers, three_kernel: one launch per phase") if loop else None,
         "fp64_warm_start": ({"ms_per_solve": round(float(np.median([wm for wm, _ in warm])), 3),
                              "iters": int(np.median([wi for _, wi in warm])),
                              "note": "x0 = previous timestep's x; values differ by up to 5 % between timesteps"}

@@ -127,6 +127,15 @@ typedef struct rp_solve_opts {
     int32_t precond;         /* RP_PRECOND_JACOBI (default) or RP_PRECOND_BLOCK_JACOBI
                                 (RP_CG, fused solve order; FP64 and both mixed forms) */
     int32_t block_size;      /* block-Jacobi rows per block, 1..RP_BJ_MAX_BLOCK (default 4) */
+    int32_t fused_loop;      /* RP_CG with Jacobi: 1 runs the iterations in one cooperative
+                                launch (the three phases of an iteration separated by
+                                grid-wide barriers instead of kernel boundaries; same
+                                arithmetic, partial sums over a smaller grid), 0 (default)
+                                one launch per phase.  Ignored (one launch per phase) with
+                                kernel timing, graph replay, block-Jacobi, or where the
+                                device cannot launch the grid cooperatively.  On MI355X the
+                                single launch measured slower at every size tried: each
+                                barrier writes back and invalidates a die's L2 per block. */
 } rp_solve_opts;
 
 typedef struct rp_solve_info {

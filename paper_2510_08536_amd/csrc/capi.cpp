@@ -71,15 +71,15 @@ namespace {
 
 void free_plan(rp_plan* p) {
     if (!p) return;
-    void* dev[] = {p->d_slot_off, p->d_row0, p->d_nf, p->d_face_off, p->d_iface_off, p->d_row_ptr, p->d_col,
-                   p->d_perm, p->d_perm_inv, p->d_nl_row_ptr, p->d_nl_col, p->d_iface_partner, p->d_recv,
+    void* dev[] = {p->d_slot_off, p->d_row0, p->d_nf, p->d_face_off, p->d_owner, p->d_nbr, p->d_iface_off,
+                   p->d_row_ptr, p->d_col, p->d_perm, p->d_perm_inv, p->d_nl_row_ptr, p->d_nl_col, p->d_iface_partner, p->d_recv,
                    p->d_val64, p->d_val32, p->d_dinv64, p->d_dinv32, p->d_r, p->d_p, p->d_q, p->d_r32,
                    p->d_p32, p->d_q32, p->d_x32, p->d_partials, p->d_st64, p->d_st32, p->d_st_outer,
                    p->d_flags, p->d_goi_k, p->d_goi_off, p->d_goi_mask, p->d_bi_st, p->d_bi_work,
                    p->d_valT, p->d_tflag, p->d_ro_perm, p->d_ro_row_ptr, p->d_ro_col, p->d_ro_sig,
                    p->d_ro_val64, p->d_ro_val32, p->d_ro_dinv64, p->d_ro_dinv32, p->d_ro_b, p->d_ro_x,
                    p->d_ro_valT, (void*)p->d_src, p->d_bj_start, p->d_bj_minv64, p->d_bj_minv32, p->d_z,
-                   p->d_z32, p->d_bj_flag};
+                   p->d_z32, p->d_bj_flag, p->d_loop_bar};
     for (void* q : dev)
         if (q) (void)hipFree(q);
     if (p->h_st64) (void)hipHostFree(p->h_st64);
@@ -474,6 +474,7 @@ void rp_solve_opts_default(rp_solve_opts* o) {
     o->graph = 0;
     o->precond = RP_PRECOND_JACOBI;
     o->block_size = 4;
+    o->fused_loop = 0;
 }
 
 int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, rp_solve_info* info,
@@ -497,6 +498,7 @@ int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, 
     RP_CHECK(o.method == RP_CG || o.precision == RP_FP64, RP_ERR_UNSUPPORTED, "BiCGStab runs in FP64 only");
     RP_CHECK(o.transpose == 0 || o.transpose == 1, RP_ERR_ARG, "transpose must be 0 or 1");
     RP_CHECK(o.graph == 0 || o.graph == 1, RP_ERR_ARG, "graph must be 0 or 1");
+    RP_CHECK(o.fused_loop == 0 || o.fused_loop == 1, RP_ERR_ARG, "fused_loop must be 0 or 1");
     RP_CHECK(o.precond == RP_PRECOND_JACOBI || o.precond == RP_PRECOND_BLOCK_JACOBI, RP_ERR_ARG,
              "precond must be RP_PRECOND_JACOBI or RP_PRECOND_BLOCK_JACOBI");
     RP_CHECK(o.precond == RP_PRECOND_JACOBI || (o.block_size >= 1 && o.block_size <= RP_BJ_MAX_BLOCK), RP_ERR_ARG,

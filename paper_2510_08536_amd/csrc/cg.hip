@@ -37,6 +37,12 @@
 
 namespace rp {
 
+// cg_loop.hip: the iterations k0 .. min(k_end, budget) in one cooperative
+// launch; *ran = false when the device cannot hold the grid at once
+template <typename T>
+int launch_cg_loop(rp_plan* p, int32_t n, const SpmvIdx& ix, const T* val, const T* dinv, T* x, T* r, T* pv, T* q,
+                   CgState<T>* st, int32_t k0, int32_t k_end, hipStream_t s, bool* ran);
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -840,8 +846,21 @@ int cg_graph(Cg<T>& c, int chunk, hipGraphExec_t* out) {
 // replay of a captured graph of `chunk` iterations (kernels past max_iter do
 // nothing); per-kernel timing always launches eagerly.
 template <typename T>
-int iterate(Cg<T>& c, int chunk, int32_t max_iter, bool graph) {
+int iterate(Cg<T>& c, int chunk, int32_t max_iter, bool graph, int32_t fused_loop) {
     const bool timed = c.plan->timing.enabled;
+    if (fused_loop == 1 && !timed && !graph && !c.bj_minv) {
+        // launches of at most LOOP_ITERS iterations keep the barrier counter
+        // (3 arrivals per block and iteration) far below 2^32
+        constexpr int64_t LOOP_ITERS = 1 << 16;
+        bool ran = true;
+        while (ran && c.h->done == CG_RUNNING && c.h->iter < max_iter) {
+            const int32_t k1 = (int32_t)std::min<int64_t>((int64_t)c.h->iter + LOOP_ITERS, max_iter);
+            RP_TRY(launch_cg_loop<T>(c.plan, c.n, c.ix, c.val, c.dinv, c.x, c.r, c.p, c.q, c.st, c.h->iter, k1, c.s,
+                                     &ran));
+            if (ran) RP_TRY(read_state(c));
+        }
+        if (ran) return RP_OK;
+    }
     hipGraphExec_t exec = nullptr;
     if (graph && !timed) RP_TRY(cg_graph(c, chunk, &exec));
     while (c.h->done == CG_RUNNING && c.h->iter < max_iter) {
@@ -949,7 +968,7 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
             break;
         }
         if (c.h->iter >= o.max_iter) break;
-        RP_TRY(iterate(c, chunk, o.max_iter, o.graph != 0));
+        RP_TRY(iterate(c, chunk, o.max_iter, o.graph != 0, o.fused_loop));
         fresh = false;
     }
     if (!fresh && c.h->done != CG_ZERO_RHS) {
@@ -1022,7 +1041,7 @@ int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, 
             start_inner = false;
         }
         const int32_t it_before = in.h->iter;
-        RP_TRY(iterate(in, chunk, o.max_iter, o.graph != 0));
+        RP_TRY(iterate(in, chunk, o.max_iter, o.graph != 0, o.fused_loop));
         total_inner = in.h->iter;
         const int32_t d = in.h->done;
         // fold the FP32 correction into x and take the FP64 residual

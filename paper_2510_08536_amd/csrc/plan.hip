@@ -493,10 +493,11 @@ int plan_build(rp_plan* p, const rp_rank_desc* share) {
     detect_windows(p, owner, nbr);
     if ((rc = upload(&d_face_off, face_off.data(), A + 1))) return rc;
     p->d_face_off = d_face_off;
+    // the face addressing stays on the device for the value gradient
     if ((rc = upload(&d_owner, owner.data(), owner.size()))) return rc;
-    tmp.ptrs.push_back(d_owner);
+    p->d_owner = d_owner;
     if ((rc = upload(&d_nbr, nbr.data(), nbr.size()))) return rc;
-    tmp.ptrs.push_back(d_nbr);
+    p->d_nbr = d_nbr;
     if ((rc = upload(&d_if_cell, if_cell.data(), if_cell.size()))) return rc;
     tmp.ptrs.push_back(d_if_cell);
     if ((rc = upload(&d_if_rank, if_rank.data(), if_rank.size()))) return rc;

@@ -144,6 +144,8 @@ struct rp_plan {
     int32_t* d_row0 = nullptr;       // [alpha+1]
     int32_t* d_nf = nullptr;         // [alpha] internal faces
     int32_t* d_face_off = nullptr;   // [alpha+1] offsets into the share's faces
+    int32_t* d_owner = nullptr;      // [faces] owner cell of each face, rank-local, concatenated
+    int32_t* d_nbr = nullptr;        // [faces] neighbour cell of each face
     int32_t* d_iface_off = nullptr;  // [alpha+1]
 
     // pattern
@@ -233,6 +235,8 @@ struct rp_plan {
     double* d_z = nullptr;             // [n_rows] z = M^-1 r of the FP64 iteration
     float* d_z32 = nullptr;            // [n_rows] of the FP32 iteration
     uint32_t* d_bj_flag = nullptr;     // set when a block is not positive definite
+
+    uint32_t* d_loop_bar = nullptr;    // abort word and per-block barrier flags of the CG loop (cg_loop.hip)
 
     // captured CG iteration chunks (rp_solve_opts.graph), [0] FP64, [1] FP32
     hipStream_t capture_stream = nullptr;

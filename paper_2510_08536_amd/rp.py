@@ -67,7 +67,8 @@ class rp_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("inner_tol", C.c_double), ("update_delta", C.c_double), ("max_iter", C.c_int32),
                 ("precision", C.c_int32), ("max_outer", C.c_int32), ("check_every", C.c_int32),
                 ("x0_zero", C.c_int32), ("max_restarts", C.c_int32), ("method", C.c_int32),
-                ("transpose", C.c_int32), ("graph", C.c_int32), ("precond", C.c_int32), ("block_size", C.c_int32)]
+                ("transpose", C.c_int32), ("graph", C.c_int32), ("precond", C.c_int32), ("block_size", C.c_int32),
+                ("fused_loop", C.c_int32)]
 
 
 class rp_solve_info(C.Structure):

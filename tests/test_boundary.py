@@ -69,7 +69,7 @@ int main(void) {
   F(rp_solve_opts, precision);
   F(rp_solve_opts, max_outer); F(rp_solve_opts, check_every); F(rp_solve_opts, x0_zero);
   F(rp_solve_opts, max_restarts); F(rp_solve_opts, method); F(rp_solve_opts, transpose); F(rp_solve_opts, graph);
-  F(rp_solve_opts, precond); F(rp_solve_opts, block_size);
+  F(rp_solve_opts, precond); F(rp_solve_opts, block_size); F(rp_solve_opts, fused_loop);
   printf("rp_device_ptrs %zu\n", sizeof(rp_device_ptrs));
   F(rp_device_ptrs, row_ptr); F(rp_device_ptrs, col); F(rp_device_ptrs, perm); F(rp_device_ptrs, nl_row_ptr);
   F(rp_device_ptrs, nl_col); F(rp_device_ptrs, val64); F(rp_device_ptrs, val32); F(rp_device_ptrs, dinv64);
@@ -102,7 +102,7 @@ def test_opts_defaults(lib_path):
     o = rp.default_opts()
     assert o.tol == 1e-8 and o.inner_tol == 1e-4 and o.precision == rp.RP_FP64 and o.check_every > 0
     assert o.update_delta == 0.1 and o.max_outer > 0 and o.method == rp.RP_CG and o.transpose == 0 and o.graph == 0
-    assert o.precond == rp.RP_PRECOND_JACOBI and o.block_size == 4
+    assert o.precond == rp.RP_PRECOND_JACOBI and o.block_size == 4 and o.fused_loop == 0
 
 
 def test_missing_library_fails_loudly():

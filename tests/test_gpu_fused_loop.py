@@ -1,0 +1,141 @@
+"""CG iterations in one cooperative launch (rp_solve_opts.fused_loop = 1)
+against the oracle and against the three-kernel iteration (fused_loop = 0).
+
+The single-launch loop does the arithmetic of the three-kernel iteration with
+per-block partial sums over a different grid, so its iterates differ from the
+three-kernel ones by reduction order only.  Bars: the oracle's bars for a
+solve (true relative residual <= 1e-8 by the oracle's SpMV, error <= 1e-6
+against the oracle's x, iteration count within rounding of the oracle's), and
+for a fixed small iteration budget the iterate agrees with the oracle's to
+1e-10 relative.  The medium case has more row groups than the cooperative
+grid holds blocks, so each block takes several groups per SpMV phase."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import share_values, oracle_system
+from gpu_util import dev_tensor, make_plan, update
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "c1": lambda: synth.build("c1"),
+    "c4fd": lambda: synth.build("c4fd"),
+    "ragged_rcb7": lambda: synth.small((17, 13, 11), ("rcb", 7), kappa=(1e-2, 1.0), seed=21, scramble=True),
+    "stretched": lambda: synth.small((12, 12, 20), ("rcb", 6), kappa=(1e-3, 1.0), seed=22, scramble=True,
+                                     stretch=100.0),
+    "chain": lambda: synth.small((300, 1, 1), ("blocks", 5, 1, 1), seed=23, walls=(True, False, False)),
+    "rcb_mixed": lambda: synth.small((40, 20, 12), ("rcb", 3), kappa=(1e-2, 1.0), seed=24),
+    "box27": lambda: synth.small((10, 9, 8), ("blocks", 2, 1, 1), kappa=(1e-2, 1.0), seed=25, stencil=27),
+}
+
+
+def _setup(w):
+    m, buf, val64, *_ = oracle_system(w)
+    plan = make_plan(w)
+    update(plan, share_values(w))
+    return m, val64, plan
+
+
+def _iters_close(a, b):
+    return abs(a - b) <= max(3, int(0.02 * b))
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_rr"])
+def test_loop_solve_matches_oracle(name, precision):
+    w = CASES[name]()
+    m, val64, plan = _setup(w)
+    b = w.rhs()
+    x_or, st, it_or, rs_or, _ = oracle.pcg(m, val64, b, tol=1e-8)
+    assert st == 0 and rs_or == 0
+    res = {}
+    for fl in (1, 0):
+        x, info = plan.solve(dev_tensor(b), tol=1e-8, precision=precision, fused_loop=fl)
+        xh = x.cpu().numpy()
+        rr = oracle.true_relres(m, val64, b, xh)
+        err = np.linalg.norm(xh - x_or) / np.linalg.norm(x_or)
+        print(f"{name} {precision} fused_loop={fl}: {info['iters']} it (oracle {it_or}), "
+              f"rel.res {rr:.2e}, err {err:.2e}")
+        assert info["status"] == 0 and info["restarts"] == 0 and rr <= 1e-8, (fl, info, rr)
+        assert abs(info["rel_res"] - rr) <= 1e-3 * rr + 1e-15
+        assert err <= 1e-6, (fl, err)
+        res[fl] = info
+    if precision == "fp64":
+        assert _iters_close(res[1]["iters"], it_or), (res[1]["iters"], it_or)
+    else:
+        assert res[1]["outer_iters"] >= 1
+    plan.close()
+
+
+@pytest.mark.parametrize("max_iter", [1, 5, 37])
+def test_loop_iteration_budget(max_iter):
+    from paper_2510_08536_amd import RP_NOT_CONVERGED
+    w = CASES["c4fd"]()
+    m, val64, plan = _setup(w)
+    b = w.rhs()
+    xo, st, it, *_ = oracle.pcg(m, val64, b, tol=1e-8, max_iter=max_iter)
+    assert st == 1 and it == max_iter
+    x, info = plan.solve(dev_tensor(b), tol=1e-8, max_iter=max_iter, fused_loop=1, check=False)
+    assert info["status"] == RP_NOT_CONVERGED and info["iters"] == max_iter, info
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    plan.close()
+
+
+def test_loop_many_groups_per_block():
+    """512k rows: more row groups than a cooperative grid holds blocks."""
+    w = synth.small((80, 80, 80), ("blocks", 2, 2, 2), kappa=(1e-2, 1.0), seed=26)
+    m, val64, plan = _setup(w)
+    b = w.rhs()
+    x_or, st, it_or, *_ = oracle.pcg(m, val64, b, tol=1e-8)
+    assert st == 0
+    for precision in ("fp64", "mixed"):
+        x, info = plan.solve(dev_tensor(b), tol=1e-8, precision=precision, fused_loop=1)
+        xh = x.cpu().numpy()
+        rr = oracle.true_relres(m, val64, b, xh)
+        err = np.linalg.norm(xh - x_or) / np.linalg.norm(x_or)
+        print(f"80^3 {precision}: {info['iters']} it (oracle {it_or}), rel.res {rr:.2e}, err {err:.2e}")
+        assert info["status"] == 0 and rr <= 1e-8 and err <= 1e-6, (info, rr, err)
+        if precision == "fp64":
+            assert _iters_close(info["iters"], it_or), (info["iters"], it_or)
+    plan.close()
+
+
+def test_loop_breakdown_on_indefinite_matrix():
+    """diag 1, coupling -2: b is the eigenvector of eigenvalue -1, so
+    (p, A p) < 0 at the first iteration, as in the oracle."""
+    from paper_2510_08536_amd import Plan, RP_ERR_BREAKDOWN
+    n = 2
+    ranks = [dict(owner=np.array([0], np.int32), neighbour=np.array([1], np.int32),
+                  iface_cell=np.zeros(0, np.int32), iface_nbr_rank=np.zeros(0, np.int32),
+                  iface_nbr_cell=np.zeros(0, np.int32))]
+    plan = Plan([n], 0, 1, ranks)
+    plan.update([np.array([1.0, 1.0])], [np.array([-2.0])], [np.zeros(0)])
+    b = np.array([1.0, 1.0])
+    m = oracle.merge([n], 0, 1, ranks)
+    v64, *_ = oracle.update(m, oracle.receive_buffer([dict(diag=[1.0, 1.0], upper=[-2.0], iface=[])]))
+    xo, st, it, *_ = oracle.pcg(m, v64, b)
+    assert st == -6
+    x, info = plan.solve(dev_tensor(b), fused_loop=1, check=False)
+    assert info["status"] == RP_ERR_BREAKDOWN and info["iters"] == it, (info, it)
+    plan.close()
+
+
+def test_loop_falls_back_where_it_does_not_apply():
+    """Graph replay, kernel timing and block-Jacobi keep the three-kernel
+    iteration when fused_loop = 1; the answers still meet the oracle's bars."""
+    from paper_2510_08536_amd import RP_KERNEL_SPMV64
+    w = CASES["ragged_rcb7"]()
+    m, val64, plan = _setup(w)
+    b = w.rhs()
+    for kw in (dict(graph=1), dict(precond="block_jacobi", block_size=4)):
+        x, info = plan.solve(dev_tensor(b), tol=1e-8, fused_loop=1, **kw)
+        rr = oracle.true_relres(m, val64, b, x.cpu().numpy())
+        assert info["status"] == 0 and rr <= 1e-8, (kw, info, rr)
+    plan.set_timing(True)
+    x, info = plan.solve(dev_tensor(b), tol=1e-8, fused_loop=1)
+    n_spmv, _ = plan.kernel_stats(RP_KERNEL_SPMV64)
+    assert n_spmv == info["iters"]       # timed: every iteration launched apart
+    plan.set_timing(False)
+    plan.close()
