@@ -6,8 +6,8 @@ code with the GPU path.
 """
 from .oracle import (OracleError, Merged, build, loaded_library, merge, receive_buffer,
                      update, spmv, pcg, bicgstab, bicgstab_csr, true_relres, value_grad, face_grad,
-                     block_starts, block_jacobi_inverse, block_jacobi_apply, pcg_block_jacobi)
+                     block_starts, block_jacobi_inverse, block_jacobi_apply, pcg_block_jacobi, AmgHierarchy)
 
 __all__ = ["OracleError", "Merged", "build", "loaded_library", "merge", "receive_buffer",
            "update", "spmv", "pcg", "bicgstab", "bicgstab_csr", "true_relres", "value_grad", "face_grad",
-           "block_starts", "block_jacobi_inverse", "block_jacobi_apply", "pcg_block_jacobi"]
+           "block_starts", "block_jacobi_inverse", "block_jacobi_apply", "pcg_block_jacobi", "AmgHierarchy"]

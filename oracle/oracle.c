@@ -630,3 +630,485 @@ done:
     free(start); free(minv); free(r); free(z); free(p); free(q);
     return status;
 }
+
+/* ------------------------------------------------------------------------ *
+ * Aggregation multigrid preconditioner (the multigrid option of the outlook
+ * in Sec. 5): unsmoothed aggregation by pairwise matching, Galerkin coarse
+ * matrices, one damped-Jacobi sweep before and after the coarse correction
+ * on every other level, a dense inverse on the coarsest level.
+ *
+ * Level 0 is the fused local block.  Level l + 1 is built from level l
+ * (n rows, CSR with ascending columns, symmetric, every row holding its
+ * diagonal) unless n <= coarse_max, which makes level l the coarsest:
+ *
+ *  1. Coupling strength of the entry (i, j), j != i, with value a < 0:
+ *     key (w, h, lo, hi) with w = -a, lo = min(i, j), hi = max(i, j),
+ *     h = fmix32(lo * 0x9E3779B1 + hi mod 2^32) (the 32-bit finaliser of
+ *     MurmurHash3, used only to break ties between equal w).  Entry e1 is
+ *     stronger than e2 when w1 > w2, or w equal and h1 > h2, or w and h
+ *     equal and (lo1, hi1) < (lo2, hi2).  Entries with a >= 0 never couple.
+ *  2. Pairwise matching in rounds (at most OR_AMG_ROUNDS): every unmatched
+ *     row picks its strongest coupling to an unmatched row (none: no pick);
+ *     rows i and j that picked each other become a pair.  The rounds stop
+ *     after one that forms no pair.
+ *  3. A row left unmatched joins the pair of its strongest coupling to a
+ *     matched row, if it has one; otherwise it stays alone.  The leader of
+ *     a pair is its smaller row; an aggregate is a pair with the rows that
+ *     joined it, or a lone row.  Aggregates are numbered by their leaders,
+ *     ascending: agg[i] is row i's coarse row.  No aggregate formed (every
+ *     row alone) is an error.
+ *  4. Galerkin coarse matrix A_c = P^T A P with P[i][agg[i]] = 1: the entry
+ *     (I, J) exists when some entry (i, j) of A has agg[i] = I, agg[j] = J;
+ *     its value sums those entries' values from 0 in ascending CSR position.
+ *     Columns ascending.  dinv = 1 / diagonal on every level.
+ *  5. The coarsest matrix (n <= coarse_max) is inverted densely by
+ *     Gauss-Jordan without pivoting in the textbook order (as the block
+ *     inverses above; A is SPD so every pivot is positive).
+ *
+ * Application y = V_l(r) on level l:
+ *  - coarsest: y_i = sum over j ascending of Cinv[i][j] r_j, from 0;
+ *  - l even ("smoothed"): x_i = omega (dinv_i r_i);
+ *    t_i = r_i - (A x)_i;  r'_I = sum of t_i over the members i of
+ *    aggregate I, ascending, from 0;  x_i = x_i + V_{l+1}(r')_{agg[i]};
+ *    y_i = x_i + omega (dinv_i (r_i - (A x)_i));
+ *  - l odd: r'_I = sum of r_i over the members, ascending, from 0;
+ *    y_i = V_{l+1}(r')_{agg[i]}.
+ * (A x)_i is the row sum of the products in column order, from 0, as in
+ * or_spmv.  The operator r -> V_0(r) is linear and symmetric (the sweeps
+ * before and after the correction are each other's adjoints, and the coarse
+ * correction is P A_c^-1 P^T on the next level); it is the PCG
+ * preconditioner M^-1.  Refresh: new level-0 values on the same pattern
+ * keep the aggregates and patterns and recompute every coarse value, dinv
+ * and the coarsest inverse (steps 4-5).
+ * ------------------------------------------------------------------------ */
+#define OR_ERR_UNSUPPORTED (-5)
+#define OR_AMG_MAX_LEVELS 40
+#define OR_AMG_ROUNDS 16
+
+typedef struct {
+    int64_t n, nnz;
+    int32_t *row_ptr, *col;
+    double *val, *dinv;
+    int32_t *agg;       /* [n] coarse row of each row (all but the coarsest) */
+    int32_t *mem_ptr;   /* [n_c + 1] members of each coarse row, ascending */
+    int32_t *mem;       /* [n] */
+    int32_t *cptr;      /* [nnz_c + 1] the coarse entry e sums val[cpos[cptr[e] .. cptr[e+1])] */
+    int32_t *cpos;      /* [nnz] */
+} or_level;
+
+typedef struct {
+    int n_levels;
+    double omega;
+    or_level lev[OR_AMG_MAX_LEVELS];
+    double* cinv;       /* dense inverse of the coarsest matrix, row-major */
+} or_amg;
+
+static uint32_t or_fmix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    x *= 0xC2B2AE35u;
+    x ^= x >> 16;
+    return x;
+}
+
+typedef struct {
+    double w;
+    uint32_t h;
+    int64_t lo, hi;
+} or_key;
+
+static or_key or_coupling(int64_t i, int64_t j, double a)
+{
+    or_key k;
+    k.w = -a;
+    k.lo = i < j ? i : j;
+    k.hi = i < j ? j : i;
+    k.h = or_fmix32((uint32_t)k.lo * 0x9E3779B1u + (uint32_t)k.hi);
+    return k;
+}
+
+static int or_stronger(const or_key* a, const or_key* b)
+{
+    if (a->w != b->w) return a->w > b->w;
+    if (a->h != b->h) return a->h > b->h;
+    if (a->lo != b->lo) return a->lo < b->lo;
+    return a->hi < b->hi;
+}
+
+/* strongest coupling of row i to a row j with (mate[j] >= 0) == want_matched; -1 if none */
+static int64_t or_strongest(const or_level* L, int64_t i, const int32_t* mate, int want_matched)
+{
+    int64_t best = -1;
+    or_key kb = {0.0, 0u, 0, 0};
+    for (int64_t p = L->row_ptr[i]; p < L->row_ptr[i + 1]; ++p) {
+        const int64_t j = L->col[p];
+        if (j == i || !(L->val[p] < 0.0)) continue;
+        if ((mate[j] >= 0) != want_matched) continue;
+        const or_key k = or_coupling(i, j, L->val[p]);
+        if (best < 0 || or_stronger(&k, &kb)) {
+            best = j;
+            kb = k;
+        }
+    }
+    return best;
+}
+
+static void or_level_free(or_level* L)
+{
+    free(L->row_ptr); free(L->col); free(L->val); free(L->dinv);
+    free(L->agg); free(L->mem_ptr); free(L->mem); free(L->cptr); free(L->cpos);
+    memset(L, 0, sizeof(*L));
+}
+
+/* steps 1-3: agg[] of level L; returns the number of aggregates */
+static int64_t or_aggregate(const or_level* L, int32_t* agg)
+{
+    const int64_t n = L->n;
+    int32_t* mate = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int32_t* pick = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int32_t* leader = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    for (int64_t i = 0; i < n; ++i) mate[i] = -1;
+    for (int round = 0; round < OR_AMG_ROUNDS; ++round) {
+        for (int64_t i = 0; i < n; ++i) pick[i] = mate[i] >= 0 ? -1 : (int32_t)or_strongest(L, i, mate, 0);
+        int64_t pairs = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t j = pick[i];
+            if (j >= 0 && pick[j] == (int32_t)i) {
+                mate[i] = j;
+                ++pairs;
+            }
+        }
+        if (pairs == 0) break;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (mate[i] >= 0) {
+            leader[i] = (int32_t)(i < mate[i] ? i : mate[i]);
+        } else {
+            const int64_t j = or_strongest(L, i, mate, 1);
+            leader[i] = j >= 0 ? (j < mate[j] ? (int32_t)j : mate[j]) : (int32_t)i;
+        }
+    }
+    int64_t nc = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (leader[i] == (int32_t)i) pick[i] = (int32_t)nc++;   /* pick[] reused: id of a leader */
+    for (int64_t i = 0; i < n; ++i) agg[i] = pick[leader[i]];
+    free(mate); free(pick); free(leader);
+    return nc;
+}
+
+/* step 4, pattern: C's row_ptr/col, L's members and contributions */
+static void or_galerkin_pattern(or_level* L, or_level* C)
+{
+    const int64_t n = L->n, nc = C->n;
+    L->mem_ptr = (int32_t*)calloc((size_t)(nc + 1), sizeof(int32_t));
+    L->mem = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    for (int64_t i = 0; i < n; ++i) L->mem_ptr[L->agg[i] + 1]++;
+    for (int64_t I = 0; I < nc; ++I) L->mem_ptr[I + 1] += L->mem_ptr[I];
+    int32_t* fill = (int32_t*)calloc((size_t)(nc + 1), sizeof(int32_t));
+    for (int64_t i = 0; i < n; ++i) L->mem[L->mem_ptr[L->agg[i]] + fill[L->agg[i]]++] = (int32_t)i;
+    free(fill);
+    /* per coarse row: the (J, position) pairs of its members' entries, sorted */
+    int64_t* key = (int64_t*)malloc(sizeof(int64_t) * (size_t)(L->nnz + 1));
+    C->row_ptr = (int32_t*)calloc((size_t)(nc + 1), sizeof(int32_t));
+    C->col = (int32_t*)malloc(sizeof(int32_t) * (size_t)(L->nnz + 1));
+    L->cpos = (int32_t*)malloc(sizeof(int32_t) * (size_t)(L->nnz + 1));
+    L->cptr = (int32_t*)malloc(sizeof(int32_t) * (size_t)(L->nnz + 2));
+    int64_t nk = 0, ne = 0;
+    for (int64_t I = 0; I < nc; ++I) {
+        const int64_t k0 = nk;
+        for (int64_t m = L->mem_ptr[I]; m < L->mem_ptr[I + 1]; ++m) {
+            const int64_t i = L->mem[m];
+            for (int64_t p = L->row_ptr[i]; p < L->row_ptr[i + 1]; ++p)
+                key[nk++] = ((int64_t)L->agg[L->col[p]] << 32) | p;
+        }
+        for (int64_t a = k0 + 1; a < nk; ++a) {   /* insertion sort of the row's keys */
+            const int64_t v = key[a];
+            int64_t b = a;
+            while (b > k0 && key[b - 1] > v) { key[b] = key[b - 1]; --b; }
+            key[b] = v;
+        }
+        for (int64_t a = k0; a < nk; ++a) {
+            const int32_t J = (int32_t)(key[a] >> 32);
+            if (a == k0 || J != (int32_t)(key[a - 1] >> 32)) {
+                L->cptr[ne] = (int32_t)a;
+                C->col[ne++] = J;
+            }
+            L->cpos[a] = (int32_t)(key[a] & 0xFFFFFFFF);
+        }
+        C->row_ptr[I + 1] = (int32_t)ne;
+    }
+    L->cptr[ne] = (int32_t)nk;
+    C->nnz = ne;
+    free(key);
+}
+
+/* step 4, values; dinv of C */
+static int or_galerkin_values(const or_level* L, or_level* C)
+{
+    for (int64_t e = 0; e < C->nnz; ++e) {
+        double s = 0.0;
+        for (int64_t t = L->cptr[e]; t < L->cptr[e + 1]; ++t) s += L->val[L->cpos[t]];
+        C->val[e] = s;
+    }
+    for (int64_t I = 0; I < C->n; ++I) {
+        double d = 0.0;
+        for (int64_t p = C->row_ptr[I]; p < C->row_ptr[I + 1]; ++p)
+            if (C->col[p] == I) d = C->val[p];
+        if (!(d > 0.0) || !isfinite(d)) return OR_ERR_BREAKDOWN;
+        C->dinv[I] = 1.0 / d;
+    }
+    return OR_OK;
+}
+
+/* step 5 */
+static int or_dense_inverse(const or_level* L, double* out)
+{
+    const int64_t n = L->n;
+    double* W = (double*)calloc((size_t)(n * n + 1), sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < n; ++j) out[i * n + j] = (i == j) ? 1.0 : 0.0;
+        for (int64_t p = L->row_ptr[i]; p < L->row_ptr[i + 1]; ++p) W[i * n + L->col[p]] = L->val[p];
+    }
+    int status = OR_OK;
+    for (int64_t k = 0; k < n && status == OR_OK; ++k) {
+        const double piv = W[k * n + k];
+        if (!(piv > 0.0) || !isfinite(piv)) { status = OR_ERR_BREAKDOWN; break; }
+        for (int64_t j = 0; j < n; ++j) {
+            W[k * n + j] = W[k * n + j] / piv;
+            out[k * n + j] = out[k * n + j] / piv;
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            if (i == k) continue;
+            const double f = W[i * n + k];
+            for (int64_t j = 0; j < n; ++j) {
+                W[i * n + j] = W[i * n + j] - f * W[k * n + j];
+                out[i * n + j] = out[i * n + j] - f * out[k * n + j];
+            }
+        }
+    }
+    free(W);
+    return status;
+}
+
+static int or_amg_values(or_amg* h)
+{
+    for (int l = 0; l + 1 < h->n_levels; ++l) {
+        const int st = or_galerkin_values(&h->lev[l], &h->lev[l + 1]);
+        if (st != OR_OK) return st;
+    }
+    return or_dense_inverse(&h->lev[h->n_levels - 1], h->cinv);
+}
+
+void or_amg_free(void* handle)
+{
+    or_amg* h = (or_amg*)handle;
+    if (!h) return;
+    for (int l = 0; l < h->n_levels; ++l) or_level_free(&h->lev[l]);
+    free(h->cinv);
+    free(h);
+}
+
+/* the hierarchy of the CSR matrix (n, row_ptr, col, val); NULL with *status
+ * set on failure (OR_ERR_UNSUPPORTED: coarsening stalled or too many levels;
+ * OR_ERR_BREAKDOWN: a coarse diagonal or pivot not positive) */
+void* or_amg_build(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val, double omega,
+                   int64_t coarse_max, int* status)
+{
+    or_amg* h = (or_amg*)calloc(1, sizeof(or_amg));
+    h->omega = omega;
+    or_level* L = &h->lev[0];
+    L->n = n;
+    L->nnz = row_ptr[n];
+    L->row_ptr = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    L->col = (int32_t*)malloc(sizeof(int32_t) * (size_t)(L->nnz + 1));
+    L->val = (double*)malloc(sizeof(double) * (size_t)(L->nnz + 1));
+    L->dinv = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+    memcpy(L->row_ptr, row_ptr, sizeof(int32_t) * (size_t)(n + 1));
+    memcpy(L->col, col, sizeof(int32_t) * (size_t)L->nnz);
+    memcpy(L->val, val, sizeof(double) * (size_t)L->nnz);
+    h->n_levels = 1;
+    *status = OR_OK;
+    for (int64_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+            if (col[p] == i) d = val[p];
+        if (!(d > 0.0) || !isfinite(d)) { *status = OR_ERR_BREAKDOWN; or_amg_free(h); return NULL; }
+        L->dinv[i] = 1.0 / d;
+    }
+    while (h->lev[h->n_levels - 1].n > coarse_max) {
+        if (h->n_levels == OR_AMG_MAX_LEVELS) { *status = OR_ERR_UNSUPPORTED; or_amg_free(h); return NULL; }
+        or_level* F = &h->lev[h->n_levels - 1];
+        or_level* C = &h->lev[h->n_levels];
+        F->agg = (int32_t*)malloc(sizeof(int32_t) * (size_t)(F->n + 1));
+        C->n = or_aggregate(F, F->agg);
+        if (C->n == F->n) { *status = OR_ERR_UNSUPPORTED; or_amg_free(h); return NULL; }
+        or_galerkin_pattern(F, C);
+        C->val = (double*)malloc(sizeof(double) * (size_t)(C->nnz + 1));
+        C->dinv = (double*)malloc(sizeof(double) * (size_t)(C->n + 1));
+        h->n_levels++;
+        const int st = or_galerkin_values(F, C);
+        if (st != OR_OK) { *status = st; or_amg_free(h); return NULL; }
+    }
+    const int64_t nL = h->lev[h->n_levels - 1].n;
+    h->cinv = (double*)malloc(sizeof(double) * (size_t)(nL * nL + 1));
+    const int st = or_dense_inverse(&h->lev[h->n_levels - 1], h->cinv);
+    if (st != OR_OK) { *status = st; or_amg_free(h); return NULL; }
+    return h;
+}
+
+/* new level-0 values on the same pattern: steps 4-5 again */
+int or_amg_refresh(void* handle, const double* val)
+{
+    or_amg* h = (or_amg*)handle;
+    or_level* L = &h->lev[0];
+    memcpy(L->val, val, sizeof(double) * (size_t)L->nnz);
+    for (int64_t i = 0; i < L->n; ++i) {
+        double d = 0.0;
+        for (int64_t p = L->row_ptr[i]; p < L->row_ptr[i + 1]; ++p)
+            if (L->col[p] == i) d = L->val[p];
+        if (!(d > 0.0) || !isfinite(d)) return OR_ERR_BREAKDOWN;
+        L->dinv[i] = 1.0 / d;
+    }
+    return or_amg_values(h);
+}
+
+int or_amg_levels(const void* handle) { return ((const or_amg*)handle)->n_levels; }
+
+void or_amg_level_sizes(const void* handle, int l, int64_t* n, int64_t* nnz)
+{
+    const or_level* L = &((const or_amg*)handle)->lev[l];
+    *n = L->n;
+    *nnz = L->nnz;
+}
+
+/* copies of level l's arrays (agg and members: [n] and [n_{l+1} + 1] / [n],
+ * not on the coarsest level); NULL pointers are skipped */
+void or_amg_level_get(const void* handle, int l, int32_t* row_ptr, int32_t* col, double* val, double* dinv,
+                      int32_t* agg, int32_t* mem_ptr, int32_t* mem)
+{
+    const or_amg* h = (const or_amg*)handle;
+    const or_level* L = &h->lev[l];
+    if (row_ptr) memcpy(row_ptr, L->row_ptr, sizeof(int32_t) * (size_t)(L->n + 1));
+    if (col) memcpy(col, L->col, sizeof(int32_t) * (size_t)L->nnz);
+    if (val) memcpy(val, L->val, sizeof(double) * (size_t)L->nnz);
+    if (dinv) memcpy(dinv, L->dinv, sizeof(double) * (size_t)L->n);
+    if (l + 1 < h->n_levels) {
+        if (agg) memcpy(agg, L->agg, sizeof(int32_t) * (size_t)L->n);
+        if (mem_ptr) memcpy(mem_ptr, L->mem_ptr, sizeof(int32_t) * (size_t)(h->lev[l + 1].n + 1));
+        if (mem) memcpy(mem, L->mem, sizeof(int32_t) * (size_t)L->n);
+    }
+}
+
+void or_amg_coarse_inverse(const void* handle, double* out)
+{
+    const or_amg* h = (const or_amg*)handle;
+    const int64_t n = h->lev[h->n_levels - 1].n;
+    memcpy(out, h->cinv, sizeof(double) * (size_t)(n * n));
+}
+
+static void or_amg_apply(const or_amg* h, int l, const double* r, double* y)
+{
+    const or_level* L = &h->lev[l];
+    const int64_t n = L->n;
+    if (l == h->n_levels - 1) {
+        for (int64_t i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int64_t j = 0; j < n; ++j) s += h->cinv[i * n + j] * r[j];
+            y[i] = s;
+        }
+        return;
+    }
+    const int64_t nc = h->lev[l + 1].n;
+    double* rc = (double*)calloc((size_t)(nc + 1), sizeof(double));
+    double* ec = (double*)calloc((size_t)(nc + 1), sizeof(double));
+    if (l % 2 == 1) {
+        for (int64_t I = 0; I < nc; ++I) {
+            double s = 0.0;
+            for (int64_t m = L->mem_ptr[I]; m < L->mem_ptr[I + 1]; ++m) s += r[L->mem[m]];
+            rc[I] = s;
+        }
+        or_amg_apply(h, l + 1, rc, ec);
+        for (int64_t i = 0; i < n; ++i) y[i] = ec[L->agg[i]];
+    } else {
+        double* x = (double*)calloc((size_t)(n + 1), sizeof(double));
+        double* t = (double*)calloc((size_t)(n + 1), sizeof(double));
+        for (int64_t i = 0; i < n; ++i) x[i] = h->omega * (L->dinv[i] * r[i]);
+        or_spmv(n, L->row_ptr, L->col, L->val, x, t);
+        for (int64_t i = 0; i < n; ++i) t[i] = r[i] - t[i];
+        for (int64_t I = 0; I < nc; ++I) {
+            double s = 0.0;
+            for (int64_t m = L->mem_ptr[I]; m < L->mem_ptr[I + 1]; ++m) s += t[L->mem[m]];
+            rc[I] = s;
+        }
+        or_amg_apply(h, l + 1, rc, ec);
+        for (int64_t i = 0; i < n; ++i) x[i] = x[i] + ec[L->agg[i]];
+        or_spmv(n, L->row_ptr, L->col, L->val, x, t);
+        for (int64_t i = 0; i < n; ++i) y[i] = x[i] + h->omega * (L->dinv[i] * (r[i] - t[i]));
+        free(x); free(t);
+    }
+    free(rc); free(ec);
+}
+
+void or_amg_vcycle(const void* handle, const double* r, double* y)
+{
+    or_amg_apply((const or_amg*)handle, 0, r, y);
+}
+
+/* PCG exactly as or_pcg, with z = M^-1 r by the hierarchy's V-cycle (level
+ * 0 of the hierarchy is the system matrix) */
+int or_pcg_amg(const void* handle, const double* b, double* x, double tol, int64_t max_iter, int max_restarts,
+               int64_t* out, double* res)
+{
+    const or_amg* h = (const or_amg*)handle;
+    const or_level* L = &h->lev[0];
+    const int64_t n = L->n;
+    double* r = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* z = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* p = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* q = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int status = OR_NOT_CONVERGED;
+    int64_t it = 0;
+    int restarts = 0;
+    const double bnorm = sqrt(dot(n, b, b));
+    if (bnorm == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        status = OR_OK;
+        goto done;
+    }
+    for (;;) {
+        or_spmv(n, L->row_ptr, L->col, L->val, x, q);
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+        if (sqrt(dot(n, r, r)) <= tol * bnorm) { status = OR_OK; break; }
+        or_amg_vcycle(h, r, z);
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i];
+        double rz = dot(n, r, z);
+        int passed = 0;
+        while (it < max_iter) {
+            or_spmv(n, L->row_ptr, L->col, L->val, p, q);
+            const double pq = dot(n, p, q);
+            if (!(pq > 0.0) || !isfinite(pq)) { status = OR_ERR_BREAKDOWN; goto done; }
+            const double a = rz / pq;
+            for (int64_t i = 0; i < n; ++i) x[i] += a * p[i];
+            for (int64_t i = 0; i < n; ++i) r[i] -= a * q[i];
+            ++it;
+            if (sqrt(dot(n, r, r)) <= tol * bnorm) { passed = 1; break; }
+            or_amg_vcycle(h, r, z);
+            const double rz_new = dot(n, r, z);
+            const double beta = rz_new / rz;
+            rz = rz_new;
+            for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        }
+        if (!passed) break;
+        if (or_true_relres(n, L->row_ptr, L->col, L->val, b, x) <= tol) { status = OR_OK; break; }
+        if (restarts >= max_restarts) break;
+        ++restarts;
+    }
+done:
+    out[0] = it;
+    out[1] = restarts;
+    res[0] = or_true_relres(n, L->row_ptr, L->col, L->val, b, x);
+    free(r); free(z); free(p); free(q);
+    return status;
+}

@@ -61,6 +61,16 @@ def loaded_library():
         lib.or_block_jacobi_apply.argtypes = [C.c_int64, _I32, C.c_int, _F64, _F64, _F64]
         lib.or_pcg_block_jacobi.argtypes = [C.c_int64, _I32, _I32, _F64, C.c_int, _I32, C.c_int, _F64, _F64,
                                             C.c_double, C.c_int64, C.c_int, _I64, _F64]
+        lib.or_amg_build.argtypes = [C.c_int64, _I32, _I32, _F64, C.c_double, C.c_int64, C.POINTER(C.c_int)]
+        lib.or_amg_build.restype = C.c_void_p
+        lib.or_amg_free.argtypes = [C.c_void_p]
+        lib.or_amg_refresh.argtypes = [C.c_void_p, _F64]
+        lib.or_amg_levels.argtypes = [C.c_void_p]
+        lib.or_amg_level_sizes.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        lib.or_amg_level_get.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 7
+        lib.or_amg_coarse_inverse.argtypes = [C.c_void_p, _F64]
+        lib.or_amg_vcycle.argtypes = [C.c_void_p, _F64, _F64]
+        lib.or_pcg_amg.argtypes = [C.c_void_p, _F64, _F64, C.c_double, C.c_int64, C.c_int, _I64, _F64]
         _lib = lib
     return _lib
 
@@ -291,3 +301,89 @@ def pcg_block_jacobi(m: Merged, val64, b, n_cells_share, bs: int, x0=None, tol=1
                                  np.ascontiguousarray(b, dtype=np.float64), x, float(tol), int(max_iter),
                                  int(max_restarts), out, res)
     return x, int(st), int(out[0]), int(out[1]), float(res[0])
+
+
+class AmgHierarchy:
+    """Aggregation multigrid hierarchy of the fused local block (the
+    multigrid preconditioner of the Sec. 5 outlook; the C source states the
+    aggregation, the Galerkin products and the V-cycle).  build() takes the
+    aggregates from the values given; refresh() keeps them and recomputes
+    every coarse value for new level-0 values on the same pattern."""
+
+    def __init__(self, m: Merged, val64, omega: float = 0.8, coarse_max: int = 256):
+        lib = loaded_library()
+        if m.nnz_nonlocal:
+            raise OracleError(-5, "AmgHierarchy (non-local block present)")
+        self._lib = lib
+        self.n = m.n_rows
+        self.omega = float(omega)
+        st = C.c_int(0)
+        col = _i32(m.col[:m.nnz_local]) if m.nnz_local else np.zeros(1, np.int32)
+        val = np.ascontiguousarray(val64[:max(m.nnz_local, 1)], dtype=np.float64)
+        self._h = lib.or_amg_build(m.n_rows, m.row_ptr, col, val, self.omega, int(coarse_max), C.byref(st))
+        if not self._h:
+            raise OracleError(st.value, "amg_build")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.or_amg_free(h)
+            self._h = None
+
+    def refresh(self, val64):
+        st = self._lib.or_amg_refresh(self._h, np.ascontiguousarray(val64, dtype=np.float64))
+        if st != 0:
+            raise OracleError(st, "amg_refresh")
+
+    @property
+    def n_levels(self) -> int:
+        return self._lib.or_amg_levels(self._h)
+
+    def level(self, l: int) -> dict:
+        """Level l: n, row_ptr, col, val, dinv, and (all but the coarsest)
+        agg, mem_ptr, mem."""
+        n, nnz = C.c_int64(), C.c_int64()
+        self._lib.or_amg_level_sizes(self._h, l, C.byref(n), C.byref(nnz))
+        n, nnz = n.value, nnz.value
+        d = dict(n=n, row_ptr=np.zeros(n + 1, np.int32), col=np.zeros(max(nnz, 1), np.int32),
+                 val=np.zeros(max(nnz, 1)), dinv=np.zeros(max(n, 1)))
+        last = l == self.n_levels - 1
+        nc = 0 if last else self.level_size(l + 1)
+        agg = np.zeros(max(n, 1), np.int32)
+        mem_ptr = np.zeros(nc + 1, np.int32)
+        mem = np.zeros(max(n, 1), np.int32)
+        P = C.c_void_p
+        self._lib.or_amg_level_get(self._h, l, d["row_ptr"].ctypes.data_as(P), d["col"].ctypes.data_as(P),
+                                   d["val"].ctypes.data_as(P), d["dinv"].ctypes.data_as(P),
+                                   agg.ctypes.data_as(P), mem_ptr.ctypes.data_as(P), mem.ctypes.data_as(P))
+        d["col"], d["val"], d["dinv"] = d["col"][:nnz], d["val"][:nnz], d["dinv"][:n]
+        if not last:
+            d.update(agg=agg[:n], mem_ptr=mem_ptr, mem=mem[:n])
+        return d
+
+    def level_size(self, l: int) -> int:
+        n, nnz = C.c_int64(), C.c_int64()
+        self._lib.or_amg_level_sizes(self._h, l, C.byref(n), C.byref(nnz))
+        return n.value
+
+    def coarse_inverse(self) -> np.ndarray:
+        nL = self.level_size(self.n_levels - 1)
+        out = np.zeros(max(nL * nL, 1))
+        self._lib.or_amg_coarse_inverse(self._h, out)
+        return out[:nL * nL].reshape(nL, nL)
+
+    def vcycle(self, r) -> np.ndarray:
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        y = np.zeros(max(self.n, 1))
+        self._lib.or_amg_vcycle(self._h, r if r.shape[0] else np.zeros(1), y)
+        return y[:self.n]
+
+    def pcg(self, b, x0=None, tol=1e-8, max_iter=100000, max_restarts=5):
+        """PCG (as pcg) with z = V-cycle(r) on the hierarchy's level-0
+        matrix.  Returns (x, status, iterations, restarts, true rel. res.)."""
+        x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64)
+        out = np.zeros(2, np.int64)
+        res = np.zeros(1)
+        st = self._lib.or_pcg_amg(self._h, np.ascontiguousarray(b, dtype=np.float64), x, float(tol),
+                                  int(max_iter), int(max_restarts), out, res)
+        return x, int(st), int(out[0]), int(out[1]), float(res[0])

@@ -9,6 +9,7 @@ import tempfile
 import pytest
 
 import oracle.oracle as oracle_mod
+import test_oracle_amg as amg_pins
 import test_oracle_pins as pins
 
 MUTANTS = {
@@ -57,6 +58,27 @@ MUTANTS = {
     "bj_apply_wrong_triangle": ("const int a = i < j ? i : j, c = i < j ? j : i;", "const int a = i, c = j;"),
     # block-Jacobi: blocks numbered from each rank's start instead of the share's
     "bj_starts_rank_local": ("if (start) start[nb] = (int32_t)(row + c);", "if (start) start[nb] = (int32_t)c;"),
+    # AMG: the weakest coupling taken for the strongest
+    "amg_weakest_coupling": ("if (a->w != b->w) return a->w > b->w;", "if (a->w != b->w) return a->w < b->w;"),
+    # AMG: unmatched rows never join a pair
+    "amg_no_joining": ("leader[i] = j >= 0 ? (j < mate[j] ? (int32_t)j : mate[j]) : (int32_t)i;",
+                       "leader[i] = (int32_t)i;"),
+    # AMG: Galerkin sum keeps only the first contribution of each coarse entry
+    "amg_galerkin_first_only": ("for (int64_t t = L->cptr[e]; t < L->cptr[e + 1]; ++t) s += L->val[L->cpos[t]];",
+                                "s = L->val[L->cpos[L->cptr[e]]];"),
+    # AMG: restriction of the smoothed level takes r instead of the residual t
+    "amg_restrict_r_not_t": ("for (int64_t m = L->mem_ptr[I]; m < L->mem_ptr[I + 1]; ++m) s += t[L->mem[m]];",
+                             "for (int64_t m = L->mem_ptr[I]; m < L->mem_ptr[I + 1]; ++m) s += r[L->mem[m]];"),
+    # AMG: post-smoothing without the damping factor
+    "amg_post_no_omega": ("y[i] = x[i] + h->omega * (L->dinv[i] * (r[i] - t[i]));",
+                          "y[i] = x[i] + (L->dinv[i] * (r[i] - t[i]));"),
+    # AMG: every level smoothed (the odd levels too)
+    "amg_all_levels_smoothed": ("if (l % 2 == 1) {", "if (l % 2 == 2) {"),
+    # AMG: prolongation adds the coarse correction of the wrong row
+    "amg_prolong_wrong_row": ("x[i] = x[i] + ec[L->agg[i]];", "x[i] = x[i] + ec[L->agg[n - 1 - i]];"),
+    # AMG: coarsest inverse without back elimination
+    "amg_inverse_no_back": ("if (i == k) continue;\n            const double f = W[i * n + k];",
+                            "if (i <= k) continue;\n            const double f = W[i * n + k];"),
 }
 
 PIN_CALLS = [
@@ -78,6 +100,11 @@ PIN_CALLS = [
     lambda: [pins.test_p11_block_inverse_against_lapack(c, bs) for c in range(len(pins.SMALL_CASES))
              for bs in (2, 4)],
     lambda: [pins.test_p11_apply_is_the_block_diagonal_solve(c, 4) for c in range(len(pins.SMALL_CASES))],
+    amg_pins.test_p12_chain4_pair_and_joiners,
+    amg_pins.test_p12_chain6_two_pairs,
+    lambda: [amg_pins.test_p12_galerkin_is_dense_ptap(nm) for nm in ("cube8_const", "box27")],
+    lambda: [amg_pins.test_p12_vcycle_is_the_multigrid_product(nm, cm)
+             for nm, cm in (("cube8_const", 256), ("box27", 100))],
 ]
 
 
