@@ -75,6 +75,10 @@ extern "C" {
 #define RP_PRECOND_BLOCK_JACOBI 1 /* M = the diagonal blocks of block_size consecutive rows,
                                      every block inside one CPU rank (CG only) */
 #define RP_BJ_MAX_BLOCK 8
+#define RP_PRECOND_AMG 2          /* M^-1 = one V-cycle of aggregation multigrid on the
+                                     whole fused system (CG only; rp_plan_amg_setup) */
+#define RP_AMG_OMEGA 0.8          /* damping of the multigrid's Jacobi sweeps */
+#define RP_AMG_COARSE_MAX 256     /* rows of the coarsest level at most (dense inverse) */
 
 /* ---- Krylov methods ------------------------------------------------------ */
 #define RP_CG 0                   /* Jacobi-PCG, symmetric positive definite A (the pressure
@@ -124,7 +128,7 @@ typedef struct rp_solve_opts {
                                 off where launches, not the SpMV, bound an iteration.
                                 Ignored while kernel timing is on and by RP_BICGSTAB
                                 (default 0) */
-    int32_t precond;         /* RP_PRECOND_JACOBI (default) or RP_PRECOND_BLOCK_JACOBI
+    int32_t precond;         /* RP_PRECOND_JACOBI (default), RP_PRECOND_BLOCK_JACOBI or RP_PRECOND_AMG
                                 (RP_CG, fused solve order; FP64 and both mixed forms) */
     int32_t block_size;      /* block-Jacobi rows per block, 1..RP_BJ_MAX_BLOCK (default 4) */
     int32_t fused_loop;      /* RP_CG with Jacobi: 1 runs the iterations in one cooperative
@@ -384,6 +388,61 @@ int rp_value_grad(rp_plan* plan, const double* lambda, const double* x, double* 
  * is not positive definite. */
 int rp_plan_block_jacobi(rp_plan* plan, int32_t block_size, int64_t* n_blocks, int32_t* start,
                          double* minv64, float* minv32);
+
+/* Aggregation multigrid preconditioner (the multigrid option of the outlook
+ * in Sec. 5) over the plan's whole fused system; needs an empty non-local
+ * block and, like CG, a symmetric matrix.
+ *
+ * Hierarchy.  Level 0 is the fused local block.  Level l (n rows) is the
+ * coarsest when n <= RP_AMG_COARSE_MAX; otherwise:
+ *  1. strength of an entry (i, j), j != i, with value a < 0: the key
+ *     (-a, h, min(i,j), max(i,j)), h = fmix32(min * 0x9E3779B1 + max mod 2^32)
+ *     (MurmurHash3's 32-bit finaliser); larger -a is stronger, then larger
+ *     h, then the smaller (min, max).  Entries with a >= 0 never couple.
+ *  2. matching rounds (at most 16, until a round forms no pair): every
+ *     unmatched row picks its strongest coupling to an unmatched row; rows
+ *     that picked each other pair up.
+ *  3. a row left unmatched joins the pair of its strongest coupling to a
+ *     matched row, else stays alone.  Aggregates (a pair with its joiners,
+ *     or a lone row) are numbered by their leaders (a pair's smaller row)
+ *     ascending: agg[i] is row i's coarse row.  No aggregate formed at all
+ *     is RP_ERR_UNSUPPORTED.
+ *  4. A_c = P^T A P (P[i][agg[i]] = 1): each coarse entry sums its fine
+ *     entries from 0 in ascending fine CSR position; columns ascending;
+ *     dinv = 1 / diagonal.
+ *  5. the coarsest matrix is inverted densely by Gauss-Jordan without
+ *     pivoting (RP_ERR_BREAKDOWN if a pivot or coarse diagonal is not > 0).
+ * V-cycle y = V_l(r): coarsest y = A_L^-1 r (row sums in column order);
+ * even l: x = omega (dinv r), t = r - A x, r'_I = sum of t over aggregate
+ * I's rows ascending, x += V_{l+1}(r')[agg], y = x + omega (dinv (r - A x));
+ * odd l: r'_I = sum of r over the members, y = V_{l+1}(r')[agg];
+ * omega = RP_AMG_OMEGA.  Row sums of A x in column order from 0.  The FP32
+ * inner solves use the same hierarchy with every value rounded to FP32.
+ *
+ * The first solve with RP_PRECOND_AMG builds the hierarchy from the values at
+ * hand; later value updates keep the aggregates and patterns and refresh the
+ * coarse values (steps 4-5) at the next such solve.  rp_plan_amg_setup
+ * rebuilds it from the current values (synchronises on stream). */
+int rp_plan_amg_setup(rp_plan* plan, void* stream);
+
+/* Number of levels of the hierarchy (0 before the first setup). */
+int rp_plan_amg_levels(const rp_plan* plan, int32_t* n_levels);
+
+/* Host copies of level l (values current for the last refresh; synchronises):
+ * n, nnz, row_ptr[n+1], col[nnz], val[nnz] (FP64), dinv[n], and, on all
+ * levels but the coarsest, agg[n], mem_ptr[n_{l+1}+1], mem[n] (the rows of
+ * each aggregate, ascending).  Any output pointer may be NULL.
+ * RP_ERR_ARG for a level outside 0..n_levels-1. */
+int rp_plan_amg_level(const rp_plan* plan, int32_t level, int64_t* n, int64_t* nnz, int32_t* row_ptr, int32_t* col,
+                      double* val, double* dinv, int32_t* agg, int32_t* mem_ptr, int32_t* mem);
+
+/* Host copy of the coarsest level's dense inverse, row-major [n_L * n_L]. */
+int rp_plan_amg_coarse_inverse(const rp_plan* plan, double* cinv);
+
+/* z = V_0(r) in FP64 for device vectors r, z of n_rows (fused order), with
+ * the hierarchy current for the plan's values (built or refreshed first);
+ * enqueued on stream. */
+int rp_plan_amg_apply(rp_plan* plan, const double* r, double* z, void* stream);
 
 /* Launch shape of the solvers' elementwise kernels (a diagnostic knob; the
  * default sizes the grid to n_rows, at most 1024 blocks).  blocks = 0 restores

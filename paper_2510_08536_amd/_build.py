@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "librp.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["plan.hip", "update.hip", "spmv.hip", "cg.hip", "grad.hip", "order.hip", "precond.hip", "cg_loop.hip", "noalloc.hip", "capi.cpp", "ipc.cpp"]
+SOURCES = ["plan.hip", "update.hip", "spmv.hip", "cg.hip", "grad.hip", "order.hip", "precond.hip", "amg.hip", "cg_loop.hip", "noalloc.hip", "capi.cpp", "ipc.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I", INCLUDE]

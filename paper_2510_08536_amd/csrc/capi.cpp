@@ -80,6 +80,7 @@ void free_plan(rp_plan* p) {
                    p->d_ro_val64, p->d_ro_val32, p->d_ro_dinv64, p->d_ro_dinv32, p->d_ro_b, p->d_ro_x,
                    p->d_ro_valT, (void*)p->d_src, p->d_bj_start, p->d_bj_minv64, p->d_bj_minv32, p->d_z,
                    p->d_z32, p->d_bj_flag, p->d_loop_bar};
+    amg_free(p);
     for (void* q : dev)
         if (q) (void)hipFree(q);
     if (p->h_st64) (void)hipHostFree(p->h_st64);
@@ -404,6 +405,81 @@ int rp_plan_block_jacobi(rp_plan* p, int32_t block_size, int64_t* n_blocks, int3
     return RP_OK;
 }
 
+int rp_plan_amg_setup(rp_plan* p, void* stream) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    RP_CHECK(p->has_values, RP_ERR_ARG, "no values yet: call rp_update_values first");
+    RP_TRY(activate(p));
+    hipStream_t s = as_stream(stream);
+    RP_TRY(values_solvable(p, s));
+    RP_TRY(amg_setup(p, s));
+    RP_HIP_TRY(hipStreamSynchronize(s));
+    return RP_OK;
+}
+
+int rp_plan_amg_levels(const rp_plan* p, int32_t* n_levels) {
+    clear_error();
+    RP_CHECK(p != nullptr && n_levels != nullptr, RP_ERR_ARG, "plan or n_levels is NULL");
+    *n_levels = p->amg ? p->amg->n_levels : 0;
+    return RP_OK;
+}
+
+int rp_plan_amg_level(const rp_plan* pc, int32_t level, int64_t* n, int64_t* nnz, int32_t* row_ptr, int32_t* col,
+                      double* val, double* dinv, int32_t* agg, int32_t* mem_ptr, int32_t* mem) {
+    clear_error();
+    RP_CHECK(pc != nullptr, RP_ERR_ARG, "plan is NULL");
+    rp_plan* p = const_cast<rp_plan*>(pc);
+    RP_CHECK(p->amg != nullptr && level >= 0 && level < p->amg->n_levels, RP_ERR_ARG,
+             "level %d outside the hierarchy (%d levels)", level, p->amg ? p->amg->n_levels : 0);
+    RP_TRY(activate(p));
+    RP_HIP_TRY(hipDeviceSynchronize());
+    const AmgHier& h = *p->amg;
+    const AmgLevel& L = h.lev[level];
+    const int64_t ln = L.n, lnnz = L.nnz;
+    if (n) *n = ln;
+    if (nnz) *nnz = lnnz;
+    const int32_t* drp = level == 0 ? p->d_row_ptr : L.row_ptr;
+    const int32_t* dcol = level == 0 ? p->d_col : L.col;
+    const double* dval = level == 0 ? p->d_val64 : L.val64;
+    const double* ddinv = level == 0 ? p->d_dinv64 : L.dinv64;
+    if (row_ptr) RP_HIP_TRY(hipMemcpy(row_ptr, drp, sizeof(int32_t) * (ln + 1), hipMemcpyDeviceToHost));
+    if (col && lnnz) RP_HIP_TRY(hipMemcpy(col, dcol, sizeof(int32_t) * lnnz, hipMemcpyDeviceToHost));
+    if (val && lnnz) RP_HIP_TRY(hipMemcpy(val, dval, sizeof(double) * lnnz, hipMemcpyDeviceToHost));
+    if (dinv && ln) RP_HIP_TRY(hipMemcpy(dinv, ddinv, sizeof(double) * ln, hipMemcpyDeviceToHost));
+    if (level + 1 < h.n_levels) {
+        const int64_t nc = h.lev[level + 1].n;
+        if (agg && ln) RP_HIP_TRY(hipMemcpy(agg, L.agg, sizeof(int32_t) * ln, hipMemcpyDeviceToHost));
+        if (mem_ptr) RP_HIP_TRY(hipMemcpy(mem_ptr, L.mem_ptr, sizeof(int32_t) * (nc + 1), hipMemcpyDeviceToHost));
+        if (mem && ln) RP_HIP_TRY(hipMemcpy(mem, L.mem, sizeof(int32_t) * ln, hipMemcpyDeviceToHost));
+    }
+    return RP_OK;
+}
+
+int rp_plan_amg_coarse_inverse(const rp_plan* pc, double* cinv) {
+    clear_error();
+    RP_CHECK(pc != nullptr && cinv != nullptr, RP_ERR_ARG, "plan or cinv is NULL");
+    rp_plan* p = const_cast<rp_plan*>(pc);
+    RP_CHECK(p->amg != nullptr, RP_ERR_ARG, "no multigrid hierarchy yet");
+    RP_TRY(activate(p));
+    RP_HIP_TRY(hipDeviceSynchronize());
+    const int64_t nL = p->amg->lev[p->amg->n_levels - 1].n;
+    RP_HIP_TRY(hipMemcpy(cinv, p->amg->cinv64, sizeof(double) * nL * nL, hipMemcpyDeviceToHost));
+    return RP_OK;
+}
+
+int rp_plan_amg_apply(rp_plan* p, const double* r, double* z, void* stream) {
+    clear_error();
+    RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
+    RP_CHECK(p->has_values, RP_ERR_ARG, "no values yet: call rp_update_values first");
+    RP_CHECK(p->n_rows == 0 || (r != nullptr && z != nullptr), RP_ERR_ARG, "r or z is NULL");
+    RP_TRY(activate(p));
+    hipStream_t s = as_stream(stream);
+    RP_TRY(values_solvable(p, s));
+    RP_TRY(amg_prepare(p, false, s));
+    if (p->n_rows == 0) return RP_OK;
+    return amg_apply<double>(p, r, z, nullptr, 0, false, nullptr, s);
+}
+
 int rp_plan_set_vec_grid(rp_plan* p, int32_t blocks) {
     clear_error();
     RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
@@ -499,8 +575,8 @@ int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, 
     RP_CHECK(o.transpose == 0 || o.transpose == 1, RP_ERR_ARG, "transpose must be 0 or 1");
     RP_CHECK(o.graph == 0 || o.graph == 1, RP_ERR_ARG, "graph must be 0 or 1");
     RP_CHECK(o.fused_loop == 0 || o.fused_loop == 1, RP_ERR_ARG, "fused_loop must be 0 or 1");
-    RP_CHECK(o.precond == RP_PRECOND_JACOBI || o.precond == RP_PRECOND_BLOCK_JACOBI, RP_ERR_ARG,
-             "precond must be RP_PRECOND_JACOBI or RP_PRECOND_BLOCK_JACOBI");
+    RP_CHECK(o.precond == RP_PRECOND_JACOBI || o.precond == RP_PRECOND_BLOCK_JACOBI || o.precond == RP_PRECOND_AMG,
+             RP_ERR_ARG, "precond must be RP_PRECOND_JACOBI, RP_PRECOND_BLOCK_JACOBI or RP_PRECOND_AMG");
     RP_CHECK(o.precond == RP_PRECOND_JACOBI || (o.block_size >= 1 && o.block_size <= RP_BJ_MAX_BLOCK), RP_ERR_ARG,
              "block_size must be in 1..%d", RP_BJ_MAX_BLOCK);
     RP_CHECK(o.precond == RP_PRECOND_JACOBI || o.method == RP_CG, RP_ERR_UNSUPPORTED,

@@ -186,8 +186,10 @@ cg_spmv_pq(int32_t n, SpmvIdx ix, const T* __restrict__ val, const T* __restrict
 }
 
 // K2: alpha = rz_k / (p, q); r -= alpha q; partials of (r, M^-1 r) ->
-// PART_RZ and (r, r) -> PART_RR.  x moves in K3, which reads p anyway.
-template <typename T>
+// PART_RZ (RZ: Jacobi M) and (r, r) -> PART_RR.  x moves in K3, which reads
+// p anyway.  Without RZ the preconditioner runs after this kernel and writes
+// the (r, z) partials itself.
+template <typename T, bool RZ = true>
 __global__ void __launch_bounds__(VEC_BLOCK)
 cg_update_r(int32_t n, int32_t k_arg, int32_t g_spmv, T* __restrict__ r, const T* __restrict__ q,
             const T* __restrict__ dinv, T* __restrict__ part, CgState<T>* st) {
@@ -234,15 +236,17 @@ cg_update_r(int32_t n, int32_t k_arg, int32_t g_spmv, T* __restrict__ r, const T
             const int32_t e = n - 1 - (i + u * di);
             rv[u] = r[e];
             qv[u] = q[e];
-            dv[u] = dinv[e];
+            dv[u] = RZ ? dinv[e] : T(0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int32_t e = n - 1 - (i + u * di);
             const T ri = rv[u] - a * qv[u];
             r[e] = ri;
-            const T zi = dv[u] * ri;
-            prz += ri * zi;
+            if (RZ) {
+                const T zi = dv[u] * ri;
+                prz += ri * zi;
+            }
             prr += ri * ri;
         }
     }
@@ -250,14 +254,16 @@ cg_update_r(int32_t n, int32_t k_arg, int32_t g_spmv, T* __restrict__ r, const T
         const int32_t e = n - 1 - i;
         const T ri = r[e] - a * q[e];
         r[e] = ri;
-        const T zi = dinv[e] * ri;
-        prz += ri * zi;
+        if (RZ) {
+            const T zi = dinv[e] * ri;
+            prz += ri * zi;
+        }
         prr += ri * ri;
     }
-    const T b1 = block_sum<T, VEC_BLOCK>(prz, red);
+    const T b1 = RZ ? block_sum<T, VEC_BLOCK>(prz, red) : T(0);
     const T b2 = block_sum<T, VEC_BLOCK>(prr, red);
     if (threadIdx.x == 0) {
-        part[PART_RZ + blockIdx.x] = b1;
+        if (RZ) part[PART_RZ + blockIdx.x] = b1;
         part[PART_RR + blockIdx.x] = b2;
     }
     if (lead) {
@@ -275,7 +281,7 @@ cg_update_r(int32_t n, int32_t k_arg, int32_t g_spmv, T* __restrict__ r, const T
 // 0 records a stop in `done`, which K3 itself never reads.
 template <typename T, bool ZMEM>
 __global__ void __launch_bounds__(VEC_BLOCK)
-cg_update_xp(int32_t n, int32_t k_arg, int32_t g_vec, int32_t resume, const T* __restrict__ r,
+cg_update_xp(int32_t n, int32_t k_arg, int32_t g_rz, int32_t g_rr, int32_t resume, const T* __restrict__ r,
              const T* __restrict__ dinv, const T* __restrict__ z, T* __restrict__ x, T* __restrict__ p,
              const T* __restrict__ part, CgState<T>* st) {
 #pragma clang fp contract(off)
@@ -287,8 +293,8 @@ cg_update_xp(int32_t n, int32_t k_arg, int32_t g_vec, int32_t resume, const T* _
         k = kk;
     }
     __shared__ T red[VEC_BLOCK / 64];
-    const T rz = sum_partials_all<T, VEC_BLOCK>(part + PART_RZ, g_vec, red);
-    const T rr = sum_partials_all<T, VEC_BLOCK>(part + PART_RR, g_vec, red);
+    const T rz = sum_partials_all<T, VEC_BLOCK>(part + PART_RZ, g_rz, red);
+    const T rr = sum_partials_all<T, VEC_BLOCK>(part + PART_RR, g_rr, red);
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     int32_t stop = CG_RUNNING;
     if (!resume && rr <= st->thresh) stop = CG_CONVERGED;
@@ -653,6 +659,10 @@ struct Cg {
     int32_t bj_bs = 0;
     bool bj_lane = false;   // aligned blocks: the lane-per-row kernels
     T* z = nullptr;
+    // multigrid (amg): M^-1 r = one V-cycle (amg.hip) into z; its last kernel
+    // writes g_rz partials of (r, z), on the SpMV grid
+    bool amg = false;
+    int32_t g_rz = 0;       // partials of (r, z) the finalize and K3 sum
 };
 
 // the matrix a solve runs on: the fused pattern in the plan's SpMV form, or
@@ -672,6 +682,7 @@ Cg<T> make_cg(rp_plan* p, const MatView& m, const T* val, const T* dinv, T* x, c
               CgState<T>* st, CgState<T>* h, int kernel_id, hipStream_t s) {
     Cg<T> c{p, (int32_t)p->n_rows, m.ix, val, dinv, x, b, r, pv, q, (T*)p->d_partials, st, h,
             kernel_id, s, spmv_grid(p->n_rows), plan_vec_grid(p), m.xw_mode, XWin{{p->xw_d[0], p->xw_d[1]}}};
+    c.g_rz = c.g_vec;
     return c;
 }
 
@@ -702,7 +713,7 @@ int launch_residual(Cg<T>& c, bool xzero, float* r32) {
 template <typename T>
 int launch_finalize(Cg<T>& c, int32_t mode, int32_t k, T tol2, T pause_frac2, int32_t max_iter = 0) {
     hipLaunchKernelGGL(cg_finalize<T>, dim3(1), dim3(VEC_BLOCK), 0, c.s, mode, k, max_iter, tol2, pause_frac2, c.g_spmv,
-                       c.g_vec, c.part, c.st);
+                       c.g_rz, c.part, c.st);
     RP_HIP_TRY(hipGetLastError());
     return RP_OK;
 }
@@ -711,7 +722,9 @@ int launch_finalize(Cg<T>& c, int32_t mode, int32_t k, T tol2, T pause_frac2, in
 // partials are still in PART_A / PART_B)
 template <typename T>
 int launch_start(Cg<T>& c, int32_t k, T tol2, T pause_frac2, int32_t max_iter) {
-    if (c.bj_minv && c.bj_lane) {
+    if (c.amg) {
+        RP_TRY(amg_apply<T>(c.plan, c.r, c.p, c.part, c.g_rz, false, nullptr, c.s));
+    } else if (c.bj_minv && c.bj_lane) {
 #define RP_LAUNCH(BS)                                                                                          \
     hipLaunchKernelGGL((cg_precond_bj_lane<T, BS, false>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, c.bj_minv, \
                        c.r, c.p, c.part)
@@ -734,7 +747,11 @@ int launch_start(Cg<T>& c, int32_t k, T tol2, T pause_frac2, int32_t max_iter) {
 template <typename T>
 int launch_resume(Cg<T>& c) {
     const int32_t k = c.h->iter - 1;
-    if (c.bj_minv) {
+    if (c.amg) {
+        RP_TRY(amg_apply<T>(c.plan, c.r, c.z, c.part, c.g_rz, true, nullptr, c.s));
+        hipLaunchKernelGGL((cg_update_xp<T, true>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, k, c.g_rz, c.g_rz, 1,
+                           c.r, c.dinv, c.z, c.x, c.p, c.part, c.st);
+    } else if (c.bj_minv) {
         if (c.bj_lane) {
 #define RP_LAUNCH(BS)                                                                                         \
     hipLaunchKernelGGL((cg_precond_bj_lane<T, BS, true>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, c.bj_minv, \
@@ -748,11 +765,11 @@ int launch_resume(Cg<T>& c) {
             RP_DISPATCH_BS(c.bj_bs, RP_LAUNCH);
 #undef RP_LAUNCH
         }
-        hipLaunchKernelGGL((cg_update_xp<T, true>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, k, c.g_vec, 1, c.r,
+        hipLaunchKernelGGL((cg_update_xp<T, true>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, k, c.g_vec, c.g_vec, 1, c.r,
                            c.dinv, c.z, c.x, c.p, c.part, c.st);
     } else {
         hipLaunchKernelGGL(cg_rz_rr<T>, dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, c.r, c.dinv, c.part);
-        hipLaunchKernelGGL((cg_update_xp<T, false>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, k, c.g_vec, 1, c.r,
+        hipLaunchKernelGGL((cg_update_xp<T, false>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, k, c.g_vec, c.g_vec, 1, c.r,
                            c.dinv, c.z, c.x, c.p, c.part, c.st);
     }
     RP_HIP_TRY(hipGetLastError());
@@ -770,7 +787,15 @@ int launch_iteration(Cg<T>& c, int32_t k, hipStream_t s) {
     RP_DISPATCH_NW(c.xw_mode, RP_LAUNCH);
 #undef RP_LAUNCH
     RP_TRY(timing_end(c.plan, c.kernel_id, s));
-    if (c.bj_minv) {
+    if (c.amg) {
+        // K2 without (r, z); the V-cycle (skipped when K2 did no update)
+        // stores z and the (r, z) partials; K3 reads z
+        hipLaunchKernelGGL((cg_update_r<T, false>), gv, bv, 0, s, c.n, k, c.g_spmv, c.r, c.q, c.dinv, c.part, c.st);
+        RP_HIP_TRY(hipGetLastError());
+        RP_TRY(amg_apply<T>(c.plan, c.r, c.z, c.part, c.g_rz, false, &c.st->kk, s));
+        hipLaunchKernelGGL((cg_update_xp<T, true>), gv, bv, 0, s, c.n, k, c.g_rz, c.g_vec, 0, c.r, c.dinv, c.z, c.x,
+                           c.p, c.part, c.st);
+    } else if (c.bj_minv) {
         if (c.bj_lane) {
 #define RP_LAUNCH(BS)                                                                                              \
     hipLaunchKernelGGL((cg_update_r_bj_lane<T, BS>), gv, bv, 0, s, c.n, k, c.g_spmv, c.bj_minv, c.r, c.q, c.z, c.part, \
@@ -784,11 +809,11 @@ int launch_iteration(Cg<T>& c, int32_t k, hipStream_t s) {
             RP_DISPATCH_BS(c.bj_bs, RP_LAUNCH);
 #undef RP_LAUNCH
         }
-        hipLaunchKernelGGL((cg_update_xp<T, true>), gv, bv, 0, s, c.n, k, c.g_vec, 0, c.r, c.dinv, c.z, c.x, c.p,
+        hipLaunchKernelGGL((cg_update_xp<T, true>), gv, bv, 0, s, c.n, k, c.g_vec, c.g_vec, 0, c.r, c.dinv, c.z, c.x, c.p,
                            c.part, c.st);
     } else {
         hipLaunchKernelGGL(cg_update_r<T>, gv, bv, 0, s, c.n, k, c.g_spmv, c.r, c.q, c.dinv, c.part, c.st);
-        hipLaunchKernelGGL((cg_update_xp<T, false>), gv, bv, 0, s, c.n, k, c.g_vec, 0, c.r, c.dinv, c.z, c.x, c.p,
+        hipLaunchKernelGGL((cg_update_xp<T, false>), gv, bv, 0, s, c.n, k, c.g_vec, c.g_vec, 0, c.r, c.dinv, c.z, c.x, c.p,
                            c.part, c.st);
     }
     RP_HIP_TRY(hipGetLastError());
@@ -848,7 +873,7 @@ int cg_graph(Cg<T>& c, int chunk, hipGraphExec_t* out) {
 template <typename T>
 int iterate(Cg<T>& c, int chunk, int32_t max_iter, bool graph, int32_t fused_loop) {
     const bool timed = c.plan->timing.enabled;
-    if (fused_loop == 1 && !timed && !graph && !c.bj_minv) {
+    if (fused_loop == 1 && !timed && !graph && !c.bj_minv && !c.amg) {
         // launches of at most LOOP_ITERS iterations keep the barrier counter
         // (3 arrivals per block and iteration) far below 2^32
         constexpr int64_t LOOP_ITERS = 1 << 16;
@@ -862,7 +887,7 @@ int iterate(Cg<T>& c, int chunk, int32_t max_iter, bool graph, int32_t fused_loo
         if (ran) return RP_OK;
     }
     hipGraphExec_t exec = nullptr;
-    if (graph && !timed) RP_TRY(cg_graph(c, chunk, &exec));
+    if (graph && !timed && !c.amg) RP_TRY(cg_graph(c, chunk, &exec));
     while (c.h->done == CG_RUNNING && c.h->iter < max_iter) {
         const int32_t k0 = c.h->iter;
         if (exec) {
@@ -886,6 +911,14 @@ void use_block_jacobi(Cg<T>& c, const rp_plan* p, const T* minv, T* z) {
     c.bj_bs = p->bj_bs;
     c.bj_lane = p->bj_aligned;
     c.z = z;
+}
+
+// the multigrid V-cycle for this solve (the hierarchy is current)
+template <typename T>
+void use_amg(Cg<T>& c, T* z) {
+    c.amg = true;
+    c.z = z;
+    c.g_rz = c.g_spmv;
 }
 
 int pending_value_error(rp_plan* p, hipStream_t s, bool need_symmetric) {
@@ -918,6 +951,8 @@ int check_solvable(rp_plan* p, hipStream_t s, bool need_symmetric = true) {
 
 }  // namespace
 
+int values_solvable(rp_plan* p, hipStream_t s) { return check_solvable(p, s, true); }
+
 int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
                hipStream_t s, bool ordered) {
     RP_TRY(check_solvable(p, s));
@@ -928,6 +963,9 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
     if (o.precond == RP_PRECOND_BLOCK_JACOBI) {
         RP_TRY(bj_prepare(p, o.block_size, s));
         use_block_jacobi(c, p, p->d_bj_minv64, p->d_z);
+    } else if (o.precond == RP_PRECOND_AMG) {
+        RP_TRY(amg_prepare(p, false, s));
+        use_amg(c, p->d_z);
     }
     const double tol2 = o.tol * o.tol;
     const int chunk = std::max(1, o.check_every);
@@ -1000,6 +1038,9 @@ int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, 
     if (o.precond == RP_PRECOND_BLOCK_JACOBI) {
         RP_TRY(bj_prepare(p, o.block_size, s));
         use_block_jacobi(in, p, p->d_bj_minv32, p->d_z32);
+    } else if (o.precond == RP_PRECOND_AMG) {
+        RP_TRY(amg_prepare(p, true, s));
+        use_amg(in, p->d_z32);
     }
     const int chunk = std::max(1, o.check_every);
 

@@ -460,6 +460,12 @@ int goi_build(rp_plan* p, hipStream_t s) {
 
 }  // namespace
 
+// exclusive scan of int32 counts for the other translation units:
+// out[0..n] with out[n] = *total (read back to the host)
+int scan_i32(const int32_t* in, int64_t n, int32_t* out, int32_t* total, hipStream_t s) {
+    return exclusive_scan(in, n, out, total, s);
+}
+
 int plan_build(rp_plan* p, const rp_rank_desc* share) {
     const int32_t A = p->alpha;
     hipStream_t s = nullptr;

@@ -92,6 +92,12 @@ std::vector<int32_t> bj_starts(const rp_plan* p, int32_t bs) {
     return st;
 }
 
+int alloc_z(rp_plan* p) {
+    if (!p->d_z) RP_HIP_TRY(hipMalloc(&p->d_z, sizeof(double) * (size_t)std::max<int64_t>(p->n_rows, 1)));
+    if (!p->d_z32) RP_HIP_TRY(hipMalloc(&p->d_z32, sizeof(float) * (size_t)std::max<int64_t>(p->n_rows, 1)));
+    return RP_OK;
+}
+
 int bj_prepare(rp_plan* p, int32_t bs, hipStream_t s) {
     if (bs < 1 || bs > BJ_MAX) {
         set_error("block size %d outside 1..%d", bs, BJ_MAX);
@@ -119,11 +125,8 @@ int bj_prepare(rp_plan* p, int32_t bs, hipStream_t s) {
         for (int32_t c : p->n_cells) aligned = aligned && c % bs == 0;
         p->bj_aligned = aligned;
     }
-    if (!p->d_z) {
-        RP_HIP_TRY(hipMalloc(&p->d_z, sizeof(double) * (size_t)std::max<int64_t>(p->n_rows, 1)));
-        RP_HIP_TRY(hipMalloc(&p->d_z32, sizeof(float) * (size_t)std::max<int64_t>(p->n_rows, 1)));
-        RP_HIP_TRY(hipMalloc(&p->d_bj_flag, sizeof(uint32_t)));
-    }
+    RP_TRY(alloc_z(p));
+    if (!p->d_bj_flag) RP_HIP_TRY(hipMalloc(&p->d_bj_flag, sizeof(uint32_t)));
     if (p->bj_version == p->values_version) return RP_OK;
     hipLaunchKernelGGL(clear_word, dim3(1), dim3(64), 0, s, p->d_bj_flag);
     const int64_t nb = p->bj_blocks;

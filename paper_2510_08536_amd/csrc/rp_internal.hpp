@@ -113,6 +113,45 @@ constexpr int N_XCD = 8;                      // MI355X: 8 accelerator dies
 constexpr int BJ_MAX = RP_BJ_MAX_BLOCK;       // largest block-Jacobi block
 
 // ---------------------------------------------------------------------------
+// aggregation multigrid hierarchy (amg.hip)
+// ---------------------------------------------------------------------------
+constexpr int AMG_MAX_LEVELS = 40;
+constexpr int AMG_COARSE_MAX = 256;   // rows of the coarsest level (dense inverse)
+constexpr int AMG_ROUNDS = 16;        // matching rounds per level at most
+
+struct AmgLevel {
+    int64_t n = 0, nnz = 0;
+    // levels >= 1 (level 0 is the plan's fused CSR and values)
+    int32_t* row_ptr = nullptr;   // [n + 1]
+    int32_t* col = nullptr;       // [nnz + SPMV_PAD]
+    double* val64 = nullptr;      // [nnz + SPMV_PAD]
+    float* val32 = nullptr;       // RNE copy
+    double* dinv64 = nullptr;     // [n] 1 / diagonal
+    float* dinv32 = nullptr;
+    int32_t* diag_pos = nullptr;  // [n] position of the diagonal entry
+    // all levels but the coarsest: the aggregates and the next level's map
+    int32_t* agg = nullptr;       // [n] coarse row of each row
+    int32_t* mem_ptr = nullptr;   // [n_c + 1] members of each coarse row,
+    int32_t* mem = nullptr;       // [n]       ascending
+    int32_t* cptr = nullptr;      // [nnz_c + 1] coarse entry e sums the values at
+    int32_t* cpos = nullptr;      // [nnz]       positions cpos[cptr[e] .. cptr[e+1])
+    // V-cycle vectors per precision: in (levels >= 1), x and t (smoothed
+    // levels), out (levels >= 1)
+    double* vec64[4] = {nullptr, nullptr, nullptr, nullptr};
+    float* vec32[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+struct AmgHier {
+    int32_t n_levels = 0;
+    AmgLevel lev[AMG_MAX_LEVELS];
+    double* cinv64 = nullptr;     // [n_L^2] inverse of the coarsest matrix, row-major
+    float* cinv32 = nullptr;      // RNE copy
+    double* cwork = nullptr;      // [n_L^2] elimination work
+    uint32_t* flag = nullptr;     // [2] pair counter / error bits
+    int64_t version = -1;         // values_version the coarse values belong to
+};
+
+// ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
 struct EventPool {
@@ -238,6 +277,8 @@ struct rp_plan {
 
     uint32_t* d_loop_bar = nullptr;    // abort word and per-block barrier flags of the CG loop (cg_loop.hip)
 
+    rp::AmgHier* amg = nullptr;        // multigrid hierarchy (RP_PRECOND_AMG), built on first use
+
     // captured CG iteration chunks (rp_solve_opts.graph), [0] FP64, [1] FP32
     hipStream_t capture_stream = nullptr;
     struct CgGraph {
@@ -312,11 +353,26 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
 int solve_bicgstab(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
                    hipStream_t s, bool ordered = false);
 int build_transpose(rp_plan* p, hipStream_t s);
+// values present, no pending value error, symmetric, no non-local block
+int values_solvable(rp_plan* p, hipStream_t s);
 int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, rp_solve_info& info,
                 hipStream_t s, bool reliable, bool ordered = false);
 // precond.hip
 // block-Jacobi tables and inverses for block size bs, current for the values
 int bj_prepare(rp_plan* p, int32_t bs, hipStream_t s);
+// the preconditioned-residual vectors d_z / d_z32
+int alloc_z(rp_plan* p);
+// amg.hip
+// hierarchy from the current values (aggregates, patterns, coarse values)
+int amg_setup(rp_plan* p, hipStream_t s);
+// hierarchy present and its values current; V-cycle vectors of one precision
+int amg_prepare(rp_plan* p, bool fp32, hipStream_t s);
+void amg_free(rp_plan* p);
+// y = V-cycle(r) on the level-0 system (fused order).  part != null: partials
+// of (r, y) -> PART_RZ (and, rr, of (r, r) -> PART_RR), n_part of them.
+// gate != null: every kernel returns when *gate < 0.
+template <typename T>
+int amg_apply(rp_plan* p, const T* r, T* y, T* part, int32_t n_part, bool rr, const int32_t* gate, hipStream_t s);
 // order.hip
 // reverse Cuthill-McKee order of a structurally symmetric pattern: perm[k] = row at position k
 std::vector<int32_t> rcm_order(int32_t n, const int32_t* row_ptr, const int32_t* col);

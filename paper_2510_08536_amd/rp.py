@@ -49,9 +49,12 @@ EXPORTED = ["rp_plan_create", "rp_plan_destroy", "rp_plan_sizes", "rp_plan_get_c
             "rp_value_grad", "rp_sync", "rp_last_error", "rp_plan_set_timing", "rp_plan_kernel_stats",
             "rp_plan_set_solve_order", "rp_plan_solve_order", "rp_rcm_order", "rp_plan_device_ptrs",
             "rp_plan_set_vec_grid", "rp_update_values_noalloc", "rp_plan_block_jacobi", "rp_plan_export_recv",
-            "rp_recv_attach", "rp_recv_write", "rp_recv_detach"]
-RP_PRECOND_JACOBI, RP_PRECOND_BLOCK_JACOBI = 0, 1
+            "rp_recv_attach", "rp_recv_write", "rp_recv_detach", "rp_plan_amg_setup", "rp_plan_amg_levels",
+            "rp_plan_amg_level", "rp_plan_amg_coarse_inverse", "rp_plan_amg_apply"]
+RP_PRECOND_JACOBI, RP_PRECOND_BLOCK_JACOBI, RP_PRECOND_AMG = 0, 1, 2
 RP_BJ_MAX_BLOCK = 8
+RP_AMG_OMEGA = 0.8
+RP_AMG_COARSE_MAX = 256
 RP_NOALLOC_MAX_RANKS = 4096
 
 
@@ -138,6 +141,11 @@ _sig = {
     "rp_recv_attach": (C.c_int, [C.POINTER(rp_ipc_handle), C.POINTER(C.c_void_p)]),
     "rp_recv_write": (C.c_int, [_P, C.c_int64, _P, C.c_int32, _P, C.c_int32, _P, _P, C.c_int32, _P]),
     "rp_recv_detach": (C.c_int, [_P]),
+    "rp_plan_amg_setup": (C.c_int, [_P, _P]),
+    "rp_plan_amg_levels": (C.c_int, [_P, _i32p]),
+    "rp_plan_amg_level": (C.c_int, [_P, C.c_int32, _i64p, _i64p, _P, _P, _P, _P, _P, _P, _P]),
+    "rp_plan_amg_coarse_inverse": (C.c_int, [_P, _P]),
+    "rp_plan_amg_apply": (C.c_int, [_P, _P, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -202,7 +210,7 @@ def _set_opts(o: rp_solve_opts, **kw) -> rp_solve_opts:
         if k == "method" and isinstance(v, str):
             v = {"cg": RP_CG, "bicgstab": RP_BICGSTAB}[v]
         if k == "precond" and isinstance(v, str):
-            v = {"jacobi": RP_PRECOND_JACOBI, "block_jacobi": RP_PRECOND_BLOCK_JACOBI}[v]
+            v = {"jacobi": RP_PRECOND_JACOBI, "block_jacobi": RP_PRECOND_BLOCK_JACOBI, "amg": RP_PRECOND_AMG}[v]
         setattr(o, k, v)
     return o
 
@@ -340,6 +348,52 @@ class Plan:
         _check(rp_plan_block_jacobi(self._h, int(block_size), C.byref(nb), _ptr(start), _ptr(m64), _ptr(m32)),
                "rp_plan_block_jacobi")
         return start, m64[:nb.value * P], m32[:nb.value * P]
+
+    # -- multigrid ---------------------------------------------------------------
+    def amg_setup(self, stream=None):
+        """Build the multigrid hierarchy from the current values."""
+        _check(rp_plan_amg_setup(self._h, _stream_handle(stream)), "rp_plan_amg_setup")
+
+    def amg_levels(self) -> int:
+        n = C.c_int32()
+        _check(rp_plan_amg_levels(self._h, C.byref(n)), "rp_plan_amg_levels")
+        return n.value
+
+    def amg_level(self, level: int) -> dict:
+        """Host copies of level `level`: n, row_ptr, col, val, dinv and (all
+        but the coarsest) agg, mem_ptr, mem."""
+        n, nnz = C.c_int64(), C.c_int64()
+        _check(rp_plan_amg_level(self._h, int(level), C.byref(n), C.byref(nnz), *([None] * 7)), "rp_plan_amg_level")
+        n, nnz = n.value, nnz.value
+        last = level == self.amg_levels() - 1
+        nc = 0
+        if not last:
+            m = C.c_int64()
+            _check(rp_plan_amg_level(self._h, int(level) + 1, C.byref(m), None, *([None] * 7)), "rp_plan_amg_level")
+            nc = m.value
+        d = dict(n=n, row_ptr=np.zeros(n + 1, np.int32), col=np.zeros(max(nnz, 1), np.int32),
+                 val=np.zeros(max(nnz, 1)), dinv=np.zeros(max(n, 1)))
+        agg, mem_ptr, mem = np.zeros(max(n, 1), np.int32), np.zeros(nc + 1, np.int32), np.zeros(max(n, 1), np.int32)
+        _check(rp_plan_amg_level(self._h, int(level), None, None, _ptr(d["row_ptr"]), _ptr(d["col"]), _ptr(d["val"]),
+                                 _ptr(d["dinv"]), _ptr(agg), _ptr(mem_ptr), _ptr(mem)), "rp_plan_amg_level")
+        d["col"], d["val"], d["dinv"] = d["col"][:nnz], d["val"][:nnz], d["dinv"][:n]
+        if not last:
+            d.update(agg=agg[:n], mem_ptr=mem_ptr, mem=mem[:n])
+        return d
+
+    def amg_coarse_inverse(self) -> np.ndarray:
+        nL = self.amg_level(self.amg_levels() - 1)["n"]
+        out = np.zeros(max(nL * nL, 1))
+        _check(rp_plan_amg_coarse_inverse(self._h, _ptr(out)), "rp_plan_amg_coarse_inverse")
+        return out[:nL * nL].reshape(nL, nL)
+
+    def amg_apply(self, r, z=None, stream=None):
+        """z = one V-cycle of the multigrid on r (float64 CUDA tensors)."""
+        torch = _torch()
+        if z is None:
+            z = torch.empty_like(r)
+        _check(rp_plan_amg_apply(self._h, _ptr(r), _ptr(z), _stream_handle(stream)), "rp_plan_amg_apply")
+        return z
 
     def set_vec_grid(self, blocks: int):
         """Fix the solvers' elementwise-kernel grid (0 = default sizing)."""

@@ -1,0 +1,202 @@
+"""Aggregation multigrid preconditioner on the GPU against the oracle.
+
+The hierarchy is integer work (matching, numbering, patterns) plus sums in a
+fixed order (Galerkin values over ascending fine positions, dense
+Gauss-Jordan in the textbook order), so every level must match the oracle's
+bit for bit: aggregates, members, patterns, values, 1/diagonals and the
+coarsest inverse.  One V-cycle is bit-exact too (row sums in column order,
+aggregate sums over the members ascending, single roundings).  Solves:
+PCG with the V-cycle reaches a true relative residual <= 1e-8 by the
+oracle's SpMV, the error against the oracle's x is <= 1e-6, and the
+iteration count is within rounding of the oracle's multigrid PCG (the only
+difference is the reduction order of the dot products); both mixed forms
+reach the same bars."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import share_values, oracle_system, random_ldu_values
+from gpu_util import dev_tensor, make_plan, update, assert_bits_equal
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "c1": lambda: synth.build("c1"),
+    "c4fd": lambda: synth.build("c4fd"),
+    "ragged_rcb7": lambda: synth.small((17, 13, 11), ("rcb", 7), kappa=(1e-2, 1.0), seed=21, scramble=True),
+    "stretched": lambda: synth.small((12, 12, 20), ("rcb", 6), kappa=(1e-3, 1.0), seed=22, scramble=True,
+                                     stretch=100.0),
+    "chain": lambda: synth.small((300, 1, 1), ("blocks", 5, 1, 1), seed=23, walls=(True, False, False)),
+    "box27": lambda: synth.small((10, 9, 8), ("blocks", 2, 1, 1), kappa=(1e-2, 1.0), seed=24, stencil=27),
+    "rcb_mixed": lambda: synth.small((40, 20, 12), ("rcb", 3), kappa=(1e-2, 1.0), seed=25),
+    "tiny": lambda: synth.small((6, 5, 4), ("blocks", 2, 1, 1), kappa=(1e-2, 1.0), seed=26),
+}
+
+
+def _setup(w, t=None):
+    m, buf, v64, *_ = oracle_system(w, t)
+    plan = make_plan(w)
+    update(plan, share_values(w, t))
+    return m, v64, plan
+
+
+def _compare_hierarchy(plan, h, what):
+    L = h.n_levels
+    assert plan.amg_levels() == L, (what, plan.amg_levels(), L)
+    for l in range(L):
+        g, o = plan.amg_level(l), h.level(l)
+        assert g["n"] == o["n"], (what, l)
+        for k in ("row_ptr", "col"):
+            assert np.array_equal(g[k], o[k]), (what, l, k)
+        assert_bits_equal(g["val"], o["val"], f"{what} level {l} val")
+        assert_bits_equal(g["dinv"], o["dinv"], f"{what} level {l} dinv")
+        if l < L - 1:
+            for k in ("agg", "mem_ptr", "mem"):
+                assert np.array_equal(g[k], o[k]), (what, l, k)
+    assert_bits_equal(plan.amg_coarse_inverse(), h.coarse_inverse(), f"{what} coarsest inverse")
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_hierarchy_and_vcycle_bit_exact(name):
+    w = CASES[name]()
+    m, v64, plan = _setup(w)
+    h = oracle.AmgHierarchy(m, v64)
+    plan.amg_setup()
+    _compare_hierarchy(plan, h, name)
+    rng = np.random.default_rng(5)
+    for _ in range(2):
+        r = rng.uniform(-1, 1, m.n_rows)
+        z = plan.amg_apply(dev_tensor(r)).cpu().numpy()
+        assert_bits_equal(z, h.vcycle(r), f"{name} V-cycle")
+    plan.close()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_rr"])
+def test_amg_pcg_matches_oracle(name, precision):
+    w = CASES[name]()
+    m, v64, plan = _setup(w)
+    b = w.rhs()
+    h = oracle.AmgHierarchy(m, v64)
+    x_or, st, it_or, rs_or, _ = h.pcg(b, tol=1e-8)
+    _, _, it_j, _, _ = oracle.pcg(m, v64, b, tol=1e-8)
+    assert st == 0 and rs_or == 0
+    x, info = plan.solve(dev_tensor(b), tol=1e-8, precision=precision, precond="amg")
+    xh = x.cpu().numpy()
+    rr = oracle.true_relres(m, v64, b, xh)
+    err = np.linalg.norm(xh - x_or) / np.linalg.norm(x_or)
+    print(f"{name} {precision}: {info['iters']} it (oracle AMG {it_or}, Jacobi {it_j}), rel.res {rr:.2e}, "
+          f"err {err:.2e}")
+    assert info["status"] == 0 and info["restarts"] == 0 and rr <= 1e-8, (info, rr)
+    assert abs(info["rel_res"] - rr) <= 1e-3 * rr + 1e-15
+    assert err <= 1e-6, err
+    if precision == "fp64":
+        assert abs(info["iters"] - it_or) <= max(2, int(0.02 * it_or)), (info["iters"], it_or)
+        if m.n_rows > 256:
+            assert info["iters"] < it_j
+    plan.close()
+
+
+def test_refresh_after_update_and_rebuild():
+    """New values: the next multigrid solve keeps the aggregates and
+    refreshes the coarse values, as the oracle's refresh; an explicit setup
+    rebuilds the aggregates from the new values, as a fresh oracle build."""
+    w = synth.small((17, 13, 11), ("rcb", 7), kappa=(1e-2, 1.0), seed=21, scramble=True, timesteps=3)
+    m, v0, plan = _setup(w, 0)
+    h = oracle.AmgHierarchy(m, v0)
+    b = w.rhs()
+    plan.solve(dev_tensor(b), tol=1e-8, precond="amg")
+    _compare_hierarchy(plan, h, "t0")
+    _, _, v1, *_ = oracle_system(w, 1)
+    update(plan, share_values(w, 1))
+    h.refresh(v1)
+    x, info = plan.solve(dev_tensor(b), tol=1e-8, precond="amg")
+    _compare_hierarchy(plan, h, "t1 refreshed")
+    assert info["status"] == 0 and oracle.true_relres(m, v1, b, x.cpu().numpy()) <= 1e-8
+    plan.amg_setup()
+    _compare_hierarchy(plan, oracle.AmgHierarchy(m, v1), "t1 rebuilt")
+    plan.close()
+
+
+def test_amg_with_timing_chunks_and_graph_request():
+    """Kernel timing, a small check interval and a graph request (the
+    multigrid path stays eager) give the same iterates."""
+    from paper_2510_08536_amd import RP_KERNEL_SPMV64
+    w = CASES["ragged_rcb7"]()
+    m, v64, plan = _setup(w)
+    b = dev_tensor(w.rhs())
+    x0, i0 = plan.solve(b, tol=1e-8, precond="amg")
+    x1, i1 = plan.solve(b, tol=1e-8, precond="amg", check_every=1, graph=1)
+    plan.set_timing(True)
+    x2, i2 = plan.solve(b, tol=1e-8, precond="amg", check_every=3)
+    n_spmv, _ = plan.kernel_stats(RP_KERNEL_SPMV64)
+    plan.set_timing(False)
+    assert i0["iters"] == i1["iters"] == i2["iters"] == n_spmv
+    assert_bits_equal(x1.cpu().numpy(), x0.cpu().numpy(), "check_every=1 + graph")
+    assert_bits_equal(x2.cpu().numpy(), x0.cpu().numpy(), "timed")
+    plan.close()
+
+
+def test_amg_iteration_budget():
+    from paper_2510_08536_amd import RP_NOT_CONVERGED
+    w = CASES["c4fd"]()
+    m, v64, plan = _setup(w)
+    b = w.rhs()
+    h = oracle.AmgHierarchy(m, v64)
+    xo, st, it, *_ = h.pcg(b, tol=1e-12, max_iter=3)
+    assert st == 1 and it == 3
+    x, info = plan.solve(dev_tensor(b), tol=1e-12, max_iter=3, precond="amg", check=False)
+    assert info["status"] == RP_NOT_CONVERGED and info["iters"] == 3
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    plan.close()
+
+
+def test_amg_rejections():
+    from paper_2510_08536_amd import RpError, RP_ERR_ARG, RP_ERR_UNSUPPORTED
+    w = CASES["ragged_rcb7"]()
+    m, v64, plan = _setup(w)
+    b = dev_tensor(w.rhs())
+    with pytest.raises(RpError) as e:
+        plan.solve(b, precond="amg", method="bicgstab")
+    assert e.value.code == RP_ERR_UNSUPPORTED
+    plan.set_solve_order("rcm")
+    with pytest.raises(RpError) as e:
+        plan.solve(b, precond="amg")
+    assert e.value.code == RP_ERR_UNSUPPORTED
+    plan.set_solve_order("fused")
+    plan.amg_setup()
+    with pytest.raises(RpError) as e:
+        plan.amg_level(plan.amg_levels())
+    assert e.value.code == RP_ERR_ARG
+    # non-symmetric values: the multigrid (like CG) refuses them
+    update(plan, random_ldu_values(w, np.random.default_rng(0)), lower=True)
+    with pytest.raises(RpError) as e:
+        plan.solve(b, precond="amg")
+    assert e.value.code == RP_ERR_UNSUPPORTED
+    with pytest.raises(RpError) as e:
+        plan.amg_setup()
+    assert e.value.code == RP_ERR_UNSUPPORTED
+    plan.close()
+
+
+def test_amg_large_hierarchy_bit_exact_and_solve():
+    """96^3 (884,736 rows, 16 ranks): the full hierarchy and one V-cycle
+    bit-exact, and the multigrid PCG against the oracle's."""
+    w = synth.build("c4")
+    m, v64, plan = _setup(w)
+    h = oracle.AmgHierarchy(m, v64)
+    plan.amg_setup()
+    _compare_hierarchy(plan, h, "c4")
+    r = np.random.default_rng(7).uniform(-1, 1, m.n_rows)
+    assert_bits_equal(plan.amg_apply(dev_tensor(r)).cpu().numpy(), h.vcycle(r), "c4 V-cycle")
+    b = w.rhs()
+    x_or, st, it_or, *_ = h.pcg(b, tol=1e-8)
+    x, info = plan.solve(dev_tensor(b), tol=1e-8, precond="amg")
+    xh = x.cpu().numpy()
+    rr = oracle.true_relres(m, v64, b, xh)
+    err = np.linalg.norm(xh - x_or) / np.linalg.norm(x_or)
+    print(f"c4: {info['iters']} it (oracle {it_or}), rel.res {rr:.2e}, err {err:.2e}, levels {h.n_levels}")
+    assert info["status"] == 0 and rr <= 1e-8 and err <= 1e-6
+    assert abs(info["iters"] - it_or) <= max(2, int(0.02 * it_or))
+    plan.close()
