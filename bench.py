@@ -290,7 +290,20 @@ def main():
                                             ("block_jacobi_8", dict(precision="fp64", precond="block_jacobi",
                                                                     block_size=8)),
                                             ("mixed_block_jacobi_4", dict(precision="mixed", precond="block_jacobi",
-                                                                          block_size=4)))
+                                                                          block_size=4)),
+                                            ("amg", dict(precision="fp64", precond="amg")),
+                                            ("mixed_amg", dict(precision="mixed", precond="amg")))
+    amg_info = None
+    if legs:
+        # multigrid hierarchy of the last step's system, built once (the legs
+        # below reuse it; a value update only refreshes its coarse values)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.amg_setup()
+        torch.cuda.synchronize()
+        amg_setup_ms = 1e3 * (time.perf_counter() - t0)
+        sizes = [plan.amg_level(l)["n"] for l in range(plan.amg_levels())]
+        amg_info = {"setup_ms": round(amg_setup_ms, 2), "levels": len(sizes), "rows_per_level": sizes}
     for label, kw in legs:
         plan.solve(b, opts=default_opts(tol=1e-8, x0_zero=1, **kw))
         ts, its = [], []
@@ -305,6 +318,19 @@ def main():
         bj[label] = {"ms_per_solve": round(float(np.median(ts)), 3), "iters": int(np.median(its))}
     for label in bj:
         bj[label]["speedup_vs_jacobi"] = round(bj["jacobi"]["ms_per_solve"] / bj[label]["ms_per_solve"], 3)
+    if amg_info is not None:
+        # value refresh: new values, then the first multigrid solve
+        # refreshes the coarse values (timed against a steady solve)
+        plan.update(*steps_vals[0])
+        e_a = ev()
+        plan.solve(b, opts=default_opts(tol=1e-8, x0_zero=1, precision="fp64", precond="amg"))
+        e_b = ev()
+        plan.solve(b, opts=default_opts(tol=1e-8, x0_zero=1, precision="fp64", precond="amg"))
+        e_c = ev()
+        torch.cuda.synchronize()
+        amg_info["refresh_ms"] = round(e_a.elapsed_time(e_b) - e_b.elapsed_time(e_c), 2)
+        plan.update(*steps_vals[n_steps_total - 1])
+        bj["amg_hierarchy"] = amg_info
     print(f"[bench] preconditioners: {bj}", flush=True)
     # CG iterations in one cooperative launch against the three-kernel
     # iteration (kernel timing off in both): per-iteration time, on systems
@@ -412,7 +438,10 @@ def main():
                      "speedup_vs_fp64": round(med(f64) / med(mr), 3)},
         "restarts_in_timed_solves": restarts,
         "preconditioners": dict(bj, note="last timestep's system, x0 = 0, tol 1e-8, 3 solves each (median); "
-                                         "block_jacobi_b: blocks of b consecutive rows inside each rank"),
+                                         "block_jacobi_b: blocks of b consecutive rows inside each rank; "
+                                         "amg: one aggregation-multigrid V-cycle per iteration (hierarchy "
+                                         "built once: amg_hierarchy.setup_ms; a value update refreshes the "
+                                         "coarse values: refresh_ms)"),
         "cg_loop": dict(loop, note="last timestep's system, x0 = 0, tol 1e-8, 3 solves each (median); "
                                    "single_launch: the iterations in one cooperative launch with grid-wide "
                                    "barriers, three_kernel: one launch per phase") if loop else None,

@@ -320,6 +320,94 @@ amg_resid(int32_t n, SpmvIdx ix, const T* __restrict__ val, const T* __restrict_
     }
 }
 
+// Coarse levels (plain CSR, 10 to 30 entries per row): blocks of AMG_CHUNK
+// consecutive rows.  The block's threads form the chunk's products val * x
+// together (coalesced over the entries) into LDS, then one thread per row
+// sums its row's products in column order from 0: the same single roundings
+// as the serial row sum.  A chunk with more than AMG_LCAP entries is summed
+// straight from memory, one thread per row.
+constexpr int AMG_CHUNK = 128;
+constexpr int AMG_LCAP = 4096;
+
+template <typename T>
+__device__ __forceinline__ bool chunk_rows(int32_t c, int32_t n, int32_t& r0, int32_t& nr) {
+    r0 = c * AMG_CHUNK;
+    nr = min(AMG_CHUNK, n - r0);
+    return nr > 0;
+}
+
+// row sum s_i = (A x)_i of the chunk's row r0 + threadIdx.x (valid for
+// threadIdx.x < nr); prod: AMG_LCAP elements of LDS
+template <typename T>
+__device__ __forceinline__ T chunk_row_sum(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                           const T* __restrict__ val, const T* __restrict__ x, int32_t r0,
+                                           int32_t nr, T* prod) {
+#pragma clang fp contract(off)
+    const int32_t t = threadIdx.x;
+    const int32_t e0 = row_ptr[r0], e1 = row_ptr[r0 + nr];
+    T s = T(0);
+    if (e1 - e0 <= AMG_LCAP) {
+        for (int32_t e = e0 + t; e < e1; e += AB) prod[e - e0] = val[e] * x[col[e]];
+        __syncthreads();
+        if (t < nr)
+            for (int32_t e = row_ptr[r0 + t]; e < row_ptr[r0 + t + 1]; ++e) s += prod[e - e0];
+        __syncthreads();   // prod is refilled by the next chunk
+    } else if (t < nr) {
+        for (int32_t e = row_ptr[r0 + t]; e < row_ptr[r0 + t + 1]; ++e) s += val[e] * x[col[e]];
+    }
+    return s;
+}
+
+// t = r - A x on a coarse level
+template <typename T>
+__global__ void __launch_bounds__(AB)
+amg_csr_resid(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+              const T* __restrict__ val, const T* __restrict__ x, const T* __restrict__ r, T* __restrict__ t,
+              const int32_t* gate) {
+#pragma clang fp contract(off)
+    __shared__ T prod[AMG_LCAP];
+    if (gate && *gate < 0) return;
+    const int32_t nch = (n + AMG_CHUNK - 1) / AMG_CHUNK;
+    for (int32_t c = xcd_block(); c < nch; c += gridDim.x) {
+        int32_t r0, nr;
+        chunk_rows<T>(c, n, r0, nr);
+        const T s = chunk_row_sum<T>(row_ptr, col, val, x, r0, nr, prod);
+        if ((int32_t)threadIdx.x < nr) {
+            const int32_t i = r0 + threadIdx.x;
+            t[i] = r[i] - s;
+        }
+    }
+}
+
+// y = x + omega (dinv (r - A x)) on a coarse level
+template <typename T>
+__global__ void __launch_bounds__(AB)
+amg_csr_post(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+             const T* __restrict__ val, const T* __restrict__ x, const T* __restrict__ r,
+             const T* __restrict__ dinv, T omega, T* __restrict__ y, const int32_t* gate) {
+#pragma clang fp contract(off)
+    __shared__ T prod[AMG_LCAP];
+    if (gate && *gate < 0) return;
+    const int32_t nch = (n + AMG_CHUNK - 1) / AMG_CHUNK;
+    for (int32_t c = xcd_block(); c < nch; c += gridDim.x) {
+        int32_t r0, nr;
+        chunk_rows<T>(c, n, r0, nr);
+        const T s = chunk_row_sum<T>(row_ptr, col, val, x, r0, nr, prod);
+        if ((int32_t)threadIdx.x < nr) {
+            const int32_t i = r0 + threadIdx.x;
+            y[i] = x[i] + omega * (dinv[i] * (r[i] - s));
+        }
+    }
+}
+
+// grid of the chunked kernels: a multiple of 8 (xcd_block), one chunk per
+// block up to 2048 blocks
+int chunk_grid(int64_t n) {
+    int64_t g = (n + AMG_CHUNK - 1) / AMG_CHUNK;
+    g = ((g + N_XCD - 1) / N_XCD) * N_XCD;
+    return (int)std::max<int64_t>(N_XCD, std::min<int64_t>(g, 2048));
+}
+
 // rc[I] = sum of v over the members of aggregate I, ascending
 template <typename T>
 __global__ void __launch_bounds__(AB)
@@ -500,9 +588,13 @@ int vcycle(rp_plan* p, int32_t l, const T* r, T* y, T* part, int32_t n_part, boo
     const T* val = l == 0 ? Prec<T>::val0(p) : Prec<T>::val(L);
     const T* dinv = l == 0 ? Prec<T>::dinv0(p) : Prec<T>::dinv(L);
     const SpmvIdx ix = level_idx(p, L, l);
-    const int gs = spmv_grid(n);
+    const int gs = spmv_grid(n), gc = chunk_grid(n);
     hipLaunchKernelGGL(amg_pre<T>, dim3(grid_of(n)), dim3(AB), 0, s, n, r, dinv, v[1], omega, gate);
-    hipLaunchKernelGGL(amg_resid<T>, dim3(gs), dim3(SPMV_BLOCK), 0, s, n, ix, val, v[1], r, v[2], gate);
+    if (l == 0)
+        hipLaunchKernelGGL(amg_resid<T>, dim3(gs), dim3(SPMV_BLOCK), 0, s, n, ix, val, v[1], r, v[2], gate);
+    else
+        hipLaunchKernelGGL(amg_csr_resid<T>, dim3(gc), dim3(AB), 0, s, n, L.row_ptr, L.col, val, v[1], r, v[2],
+                           gate);
     hipLaunchKernelGGL(amg_restrict<T>, dim3(grid_of(nc)), dim3(AB), 0, s, nc, L.mem_ptr, L.mem, v[2], cv[0], gate);
     RP_HIP_TRY(hipGetLastError());
     RP_TRY(vcycle<T>(p, l + 1, cv[0], cv[3], nullptr, 0, false, gate, s));
@@ -512,7 +604,10 @@ int vcycle(rp_plan* p, int32_t l, const T* r, T* y, T* part, int32_t n_part, boo
                        y, part, gate)
     if (want && rr) RP_LAUNCH(true, true);
     else if (want) RP_LAUNCH(true, false);
-    else RP_LAUNCH(false, false);
+    else if (l == 0) RP_LAUNCH(false, false);
+    else
+        hipLaunchKernelGGL(amg_csr_post<T>, dim3(gc), dim3(AB), 0, s, n, L.row_ptr, L.col, val, v[1], r, dinv, omega,
+                           y, gate);
 #undef RP_LAUNCH
     RP_HIP_TRY(hipGetLastError());
     return RP_OK;
