@@ -78,7 +78,7 @@ extern "C" {
 #define RP_PRECOND_AMG 2          /* M^-1 = one V-cycle of aggregation multigrid on the
                                      whole fused system (CG only; rp_plan_amg_setup) */
 #define RP_AMG_OMEGA 0.8          /* damping of the multigrid's Jacobi sweeps */
-#define RP_AMG_COARSE_MAX 256     /* rows of the coarsest level at most (dense inverse) */
+#define RP_AMG_COARSE_MAX 64      /* rows of the coarsest level at most (dense inverse) */
 
 /* ---- Krylov methods ------------------------------------------------------ */
 #define RP_CG 0                   /* Jacobi-PCG, symmetric positive definite A (the pressure

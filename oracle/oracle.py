@@ -310,7 +310,7 @@ class AmgHierarchy:
     aggregates from the values given; refresh() keeps them and recomputes
     every coarse value for new level-0 values on the same pattern."""
 
-    def __init__(self, m: Merged, val64, omega: float = 0.8, coarse_max: int = 256):
+    def __init__(self, m: Merged, val64, omega: float = 0.8, coarse_max: int = 64):
         lib = loaded_library()
         if m.nnz_nonlocal:
             raise OracleError(-5, "AmgHierarchy (non-local block present)")

@@ -116,7 +116,7 @@ constexpr int BJ_MAX = RP_BJ_MAX_BLOCK;       // largest block-Jacobi block
 // aggregation multigrid hierarchy (amg.hip)
 // ---------------------------------------------------------------------------
 constexpr int AMG_MAX_LEVELS = 40;
-constexpr int AMG_COARSE_MAX = 256;   // rows of the coarsest level (dense inverse)
+constexpr int AMG_COARSE_MAX = RP_AMG_COARSE_MAX;   // rows of the coarsest level (dense inverse)
 constexpr int AMG_ROUNDS = 16;        // matching rounds per level at most
 
 struct AmgLevel {

@@ -54,7 +54,7 @@ EXPORTED = ["rp_plan_create", "rp_plan_destroy", "rp_plan_sizes", "rp_plan_get_c
 RP_PRECOND_JACOBI, RP_PRECOND_BLOCK_JACOBI, RP_PRECOND_AMG = 0, 1, 2
 RP_BJ_MAX_BLOCK = 8
 RP_AMG_OMEGA = 0.8
-RP_AMG_COARSE_MAX = 256
+RP_AMG_COARSE_MAX = 64
 RP_NOALLOC_MAX_RANKS = 4096
 
 
