@@ -504,6 +504,28 @@ amg_coarse(int32_t n, const T* __restrict__ cinv, const T* __restrict__ r, T* __
     }
 }
 
+// the level-0 system of a hierarchy: the fused pattern (with its
+// offset-coded SpMV form) or the solve-order copy (plain CSR)
+struct Src {
+    int64_t nnz;
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const double* val64;
+    const float* val32;
+    const double* dinv64;
+    const float* dinv32;
+    SpmvIdx ix;
+};
+
+Src source(const rp_plan* p, bool ordered) {
+    if (ordered)
+        return Src{p->nnz, p->d_ro_row_ptr, p->d_ro_col, p->d_ro_val64, p->d_ro_val32, p->d_ro_dinv64,
+                   p->d_ro_dinv32, SpmvIdx{p->d_ro_row_ptr, p->d_ro_col, nullptr, nullptr, nullptr}};
+    return Src{p->nnz, p->d_row_ptr, p->d_col, p->d_val64, p->d_val32, p->d_dinv64, p->d_dinv32, spmv_idx(p)};
+}
+
+AmgHier*& hier(rp_plan* p, bool ordered) { return ordered ? p->amg_ro : p->amg; }
+
 template <typename T>
 struct Prec;
 template <>
@@ -512,8 +534,8 @@ struct Prec<double> {
     static const double* dinv(const AmgLevel& L) { return L.dinv64; }
     static double** vec(AmgLevel& L) { return L.vec64; }
     static const double* cinv(const AmgHier& h) { return h.cinv64; }
-    static const double* val0(const rp_plan* p) { return p->d_val64; }
-    static const double* dinv0(const rp_plan* p) { return p->d_dinv64; }
+    static const double* val0(const Src& q) { return q.val64; }
+    static const double* dinv0(const Src& q) { return q.dinv64; }
 };
 template <>
 struct Prec<float> {
@@ -521,8 +543,8 @@ struct Prec<float> {
     static const float* dinv(const AmgLevel& L) { return L.dinv32; }
     static float** vec(AmgLevel& L) { return L.vec32; }
     static const float* cinv(const AmgHier& h) { return h.cinv32; }
-    static const float* val0(const rp_plan* p) { return p->d_val32; }
-    static const float* dinv0(const rp_plan* p) { return p->d_dinv32; }
+    static const float* val0(const Src& q) { return q.val32; }
+    static const float* dinv0(const Src& q) { return q.dinv32; }
 };
 
 template <typename T>
@@ -548,16 +570,15 @@ int alloc_vectors(AmgHier& h) {
     return RP_OK;
 }
 
-SpmvIdx level_idx(const rp_plan* p, const AmgLevel& L, int32_t l) {
-    if (l == 0) return spmv_idx(p);
+SpmvIdx level_idx(const Src& q, const AmgLevel& L, int32_t l) {
+    if (l == 0) return q.ix;
     return SpmvIdx{L.row_ptr, L.col, nullptr, nullptr, nullptr};
 }
 
 // y = V_l(r) on stream s (level 0: r and y are the solve's vectors)
 template <typename T>
-int vcycle(rp_plan* p, int32_t l, const T* r, T* y, T* part, int32_t n_part, bool rr, const int32_t* gate,
-           hipStream_t s) {
-    AmgHier& h = *p->amg;
+int vcycle(AmgHier& h, const Src& q, int32_t l, const T* r, T* y, T* part, int32_t n_part, bool rr,
+           const int32_t* gate, hipStream_t s) {
     AmgLevel& L = h.lev[l];
     const int32_t n = (int32_t)L.n;
     const T omega = (T)RP_AMG_OMEGA;
@@ -579,15 +600,15 @@ int vcycle(rp_plan* p, int32_t l, const T* r, T* y, T* part, int32_t n_part, boo
     if (l % 2 == 1) {
         hipLaunchKernelGGL(amg_restrict<T>, dim3(grid_of(nc)), dim3(AB), 0, s, nc, L.mem_ptr, L.mem, r, cv[0], gate);
         RP_HIP_TRY(hipGetLastError());
-        RP_TRY(vcycle<T>(p, l + 1, cv[0], cv[3], nullptr, 0, false, gate, s));
+        RP_TRY(vcycle<T>(h, q, l + 1, cv[0], cv[3], nullptr, 0, false, gate, s));
         hipLaunchKernelGGL((amg_prolong<T, false>), dim3(grid_of(n)), dim3(AB), 0, s, n, L.agg, cv[3], y, gate);
         RP_HIP_TRY(hipGetLastError());
         return RP_OK;
     }
     T** v = Prec<T>::vec(L);
-    const T* val = l == 0 ? Prec<T>::val0(p) : Prec<T>::val(L);
-    const T* dinv = l == 0 ? Prec<T>::dinv0(p) : Prec<T>::dinv(L);
-    const SpmvIdx ix = level_idx(p, L, l);
+    const T* val = l == 0 ? Prec<T>::val0(q) : Prec<T>::val(L);
+    const T* dinv = l == 0 ? Prec<T>::dinv0(q) : Prec<T>::dinv(L);
+    const SpmvIdx ix = level_idx(q, L, l);
     const int gs = spmv_grid(n), gc = chunk_grid(n);
     hipLaunchKernelGGL(amg_pre<T>, dim3(grid_of(n)), dim3(AB), 0, s, n, r, dinv, v[1], omega, gate);
     if (l == 0)
@@ -597,7 +618,7 @@ int vcycle(rp_plan* p, int32_t l, const T* r, T* y, T* part, int32_t n_part, boo
                            gate);
     hipLaunchKernelGGL(amg_restrict<T>, dim3(grid_of(nc)), dim3(AB), 0, s, nc, L.mem_ptr, L.mem, v[2], cv[0], gate);
     RP_HIP_TRY(hipGetLastError());
-    RP_TRY(vcycle<T>(p, l + 1, cv[0], cv[3], nullptr, 0, false, gate, s));
+    RP_TRY(vcycle<T>(h, q, l + 1, cv[0], cv[3], nullptr, 0, false, gate, s));
     hipLaunchKernelGGL((amg_prolong<T, true>), dim3(grid_of(n)), dim3(AB), 0, s, n, L.agg, cv[3], v[1], gate);
 #define RP_LAUNCH(PT, RRF)                                                                                    \
     hipLaunchKernelGGL((amg_post<T, PT, RRF>), dim3(gs), dim3(SPMV_BLOCK), 0, s, n, ix, val, v[1], r, dinv, omega, \
@@ -639,13 +660,12 @@ void free_level(AmgLevel& L) {
 }
 
 // level l + 1 from level l (its CSR: row_ptr, col, val64)
-int coarsen(rp_plan* p, int32_t l, hipStream_t s) {
-    AmgHier& h = *p->amg;
+int coarsen(AmgHier& h, const Src& q, int32_t l, hipStream_t s) {
     AmgLevel& L = h.lev[l];
     const int32_t n = (int32_t)L.n;
-    const int32_t* rp_ = l == 0 ? p->d_row_ptr : L.row_ptr;
-    const int32_t* cl = l == 0 ? p->d_col : L.col;
-    const double* vl = l == 0 ? p->d_val64 : L.val64;
+    const int32_t* rp_ = l == 0 ? q.row_ptr : L.row_ptr;
+    const int32_t* cl = l == 0 ? q.col : L.col;
+    const double* vl = l == 0 ? q.val64 : L.val64;
     struct Tmp {   // work arrays of this call, freed on every return
         std::vector<void*> q;
         ~Tmp() {
@@ -740,12 +760,11 @@ int coarsen(rp_plan* p, int32_t l, hipStream_t s) {
 }
 
 // coarse values, diagonals and the coarsest inverse from the plan's values
-int refresh(rp_plan* p, hipStream_t s) {
-    AmgHier& h = *p->amg;
+int refresh(AmgHier& h, const Src& q, int64_t version, hipStream_t s) {
     hipLaunchKernelGGL(amg_fill, dim3(1), dim3(AB), 0, s, 1, 0, (int32_t*)h.flag);
     for (int32_t l = 0; l + 1 < h.n_levels; ++l) {
         AmgLevel &L = h.lev[l], &C = h.lev[l + 1];
-        const double* fine = l == 0 ? p->d_val64 : L.val64;
+        const double* fine = l == 0 ? q.val64 : L.val64;
         hipLaunchKernelGGL(amg_gvals, dim3(grid_of(C.nnz)), dim3(AB), 0, s, (int32_t)C.nnz, L.cptr, L.cpos, fine,
                            C.val64, C.val32);
         hipLaunchKernelGGL(amg_gdiag, dim3(grid_of(C.n)), dim3(AB), 0, s, (int32_t)C.n, C.diag_pos, C.val64, C.dinv64,
@@ -753,9 +772,9 @@ int refresh(rp_plan* p, hipStream_t s) {
         RP_HIP_TRY(hipGetLastError());
     }
     const AmgLevel& Lc = h.lev[h.n_levels - 1];
-    const int32_t* rp_ = h.n_levels == 1 ? p->d_row_ptr : Lc.row_ptr;
-    const int32_t* cl = h.n_levels == 1 ? p->d_col : Lc.col;
-    const double* vl = h.n_levels == 1 ? p->d_val64 : Lc.val64;
+    const int32_t* rp_ = h.n_levels == 1 ? q.row_ptr : Lc.row_ptr;
+    const int32_t* cl = h.n_levels == 1 ? q.col : Lc.col;
+    const double* vl = h.n_levels == 1 ? q.val64 : Lc.val64;
     hipLaunchKernelGGL(amg_dense_inverse, dim3(1), dim3(GJ_THREADS), 0, s, (int32_t)Lc.n, rp_, cl, vl, h.cwork,
                        h.cinv64, h.cinv32, h.flag);
     RP_HIP_TRY(hipGetLastError());
@@ -766,50 +785,57 @@ int refresh(rp_plan* p, hipStream_t s) {
         set_error("multigrid: a coarse diagonal or a pivot of the coarsest inverse is not positive");
         return RP_ERR_BREAKDOWN;
     }
-    h.version = p->values_version;
+    h.version = version;
     return RP_OK;
+}
+
+void free_hier(AmgHier*& hp) {
+    if (!hp) return;
+    AmgHier& h = *hp;
+    for (int32_t l = 0; l < h.n_levels; ++l) free_level(h.lev[l]);
+    for (void* a : {(void*)h.cinv64, (void*)h.cinv32, (void*)h.cwork, (void*)h.flag})
+        if (a) (void)hipFree(a);
+    delete hp;
+    hp = nullptr;
 }
 
 }  // namespace
 
 void amg_free(rp_plan* p) {
-    if (!p->amg) return;
-    AmgHier& h = *p->amg;
-    for (int32_t l = 0; l < h.n_levels; ++l) free_level(h.lev[l]);
-    for (void* a : {(void*)h.cinv64, (void*)h.cinv32, (void*)h.cwork, (void*)h.flag})
-        if (a) (void)hipFree(a);
-    delete p->amg;
-    p->amg = nullptr;
+    free_hier(p->amg);
+    free_hier(p->amg_ro);
 }
 
-int amg_setup(rp_plan* p, hipStream_t s) {
+int amg_setup(rp_plan* p, hipStream_t s, bool ordered) {
     if (p->nnz_nl > 0) {
         set_error("multigrid needs the whole system on the GPU (the share has a non-local block)");
         return RP_ERR_UNSUPPORTED;
     }
-    amg_free(p);
-    p->amg = new AmgHier();
-    AmgHier& h = *p->amg;
+    AmgHier*& hp = hier(p, ordered);
+    free_hier(hp);
+    hp = new AmgHier();
+    AmgHier& h = *hp;
+    const Src q = source(p, ordered);
     int rc = RP_OK;
     auto fail = [&](int code) {
-        amg_free(p);
+        free_hier(hp);
         return code;
     };
     h.flag = dalloc<uint32_t>(2);
     if (!h.flag) return fail((set_error("out of device memory building the multigrid"), RP_ERR_HIP));
     h.lev[0].n = p->n_rows;
-    h.lev[0].nnz = p->nnz;
+    h.lev[0].nnz = q.nnz;
     h.n_levels = 1;
     while (h.lev[h.n_levels - 1].n > AMG_COARSE_MAX) {
         if (h.n_levels == AMG_MAX_LEVELS) {
             set_error("multigrid: more than %d levels", AMG_MAX_LEVELS);
             return fail(RP_ERR_UNSUPPORTED);
         }
-        if ((rc = coarsen(p, h.n_levels - 1, s)) != RP_OK) return fail(rc);
+        if ((rc = coarsen(h, q, h.n_levels - 1, s)) != RP_OK) return fail(rc);
         h.n_levels += 1;
         // the coarse values now, so the next level's matching sees them
         AmgLevel &L = h.lev[h.n_levels - 2], &C = h.lev[h.n_levels - 1];
-        const double* fine = h.n_levels == 2 ? p->d_val64 : L.val64;
+        const double* fine = h.n_levels == 2 ? q.val64 : L.val64;
         hipLaunchKernelGGL(amg_gvals, dim3(grid_of(C.nnz)), dim3(AB), 0, s, (int32_t)C.nnz, L.cptr, L.cpos, fine,
                            C.val64, C.val32);
         RP_HIP_TRY(hipGetLastError());
@@ -820,26 +846,29 @@ int amg_setup(rp_plan* p, hipStream_t s) {
     h.cwork = dalloc<double>(nL * nL);
     if (!h.cinv64 || !h.cinv32 || !h.cwork)
         return fail((set_error("out of device memory building the multigrid"), RP_ERR_HIP));
-    if ((rc = refresh(p, s)) != RP_OK) return fail(rc);
+    if ((rc = refresh(h, q, p->values_version, s)) != RP_OK) return fail(rc);
     return RP_OK;
 }
 
-int amg_prepare(rp_plan* p, bool fp32, hipStream_t s) {
+int amg_prepare(rp_plan* p, bool fp32, hipStream_t s, bool ordered) {
     RP_TRY(alloc_z(p));
-    if (!p->amg) RP_TRY(amg_setup(p, s));
-    if (p->amg->version != p->values_version) RP_TRY(refresh(p, s));
-    if (fp32) RP_TRY(alloc_vectors<float>(*p->amg));
-    else RP_TRY(alloc_vectors<double>(*p->amg));
+    AmgHier*& hp = hier(p, ordered);
+    if (!hp) RP_TRY(amg_setup(p, s, ordered));
+    if (hp->version != p->values_version) RP_TRY(refresh(*hp, source(p, ordered), p->values_version, s));
+    if (fp32) RP_TRY(alloc_vectors<float>(*hp));
+    else RP_TRY(alloc_vectors<double>(*hp));
     return RP_OK;
 }
 
 template <typename T>
-int amg_apply(rp_plan* p, const T* r, T* y, T* part, int32_t n_part, bool rr, const int32_t* gate, hipStream_t s) {
-    return vcycle<T>(p, 0, r, y, part, n_part, rr, gate, s);
+int amg_apply(rp_plan* p, const T* r, T* y, T* part, int32_t n_part, bool rr, const int32_t* gate, hipStream_t s,
+              bool ordered) {
+    return vcycle<T>(*hier(p, ordered), source(p, ordered), 0, r, y, part, n_part, rr, gate, s);
 }
 
 template int amg_apply<double>(rp_plan*, const double*, double*, double*, int32_t, bool, const int32_t*,
-                               hipStream_t);
-template int amg_apply<float>(rp_plan*, const float*, float*, float*, int32_t, bool, const int32_t*, hipStream_t);
+                               hipStream_t, bool);
+template int amg_apply<float>(rp_plan*, const float*, float*, float*, int32_t, bool, const int32_t*, hipStream_t,
+                              bool);
 
 }  // namespace rp

@@ -581,7 +581,7 @@ int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, 
              "block_size must be in 1..%d", RP_BJ_MAX_BLOCK);
     RP_CHECK(o.precond == RP_PRECOND_JACOBI || o.method == RP_CG, RP_ERR_UNSUPPORTED,
              "block-Jacobi is built for CG (RP_CG) only");
-    RP_CHECK(o.precond == RP_PRECOND_JACOBI || p->ro_mode == 0, RP_ERR_UNSUPPORTED,
+    RP_CHECK(o.precond != RP_PRECOND_BLOCK_JACOBI || p->ro_mode == 0, RP_ERR_UNSUPPORTED,
              "block-Jacobi runs in the fused row order only (solve order 0)");
     RP_TRY(activate(p));
     hipStream_t s = as_stream(stream);

@@ -662,6 +662,7 @@ struct Cg {
     // multigrid (amg): M^-1 r = one V-cycle (amg.hip) into z; its last kernel
     // writes g_rz partials of (r, z), on the SpMV grid
     bool amg = false;
+    bool amg_ordered = false;   // the hierarchy of the solve-order copy
     int32_t g_rz = 0;       // partials of (r, z) the finalize and K3 sum
 };
 
@@ -723,7 +724,7 @@ int launch_finalize(Cg<T>& c, int32_t mode, int32_t k, T tol2, T pause_frac2, in
 template <typename T>
 int launch_start(Cg<T>& c, int32_t k, T tol2, T pause_frac2, int32_t max_iter) {
     if (c.amg) {
-        RP_TRY(amg_apply<T>(c.plan, c.r, c.p, c.part, c.g_rz, false, nullptr, c.s));
+        RP_TRY(amg_apply<T>(c.plan, c.r, c.p, c.part, c.g_rz, false, nullptr, c.s, c.amg_ordered));
     } else if (c.bj_minv && c.bj_lane) {
 #define RP_LAUNCH(BS)                                                                                          \
     hipLaunchKernelGGL((cg_precond_bj_lane<T, BS, false>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, c.bj_minv, \
@@ -748,7 +749,7 @@ template <typename T>
 int launch_resume(Cg<T>& c) {
     const int32_t k = c.h->iter - 1;
     if (c.amg) {
-        RP_TRY(amg_apply<T>(c.plan, c.r, c.z, c.part, c.g_rz, true, nullptr, c.s));
+        RP_TRY(amg_apply<T>(c.plan, c.r, c.z, c.part, c.g_rz, true, nullptr, c.s, c.amg_ordered));
         hipLaunchKernelGGL((cg_update_xp<T, true>), dim3(c.g_vec), dim3(VEC_BLOCK), 0, c.s, c.n, k, c.g_rz, c.g_rz, 1,
                            c.r, c.dinv, c.z, c.x, c.p, c.part, c.st);
     } else if (c.bj_minv) {
@@ -792,7 +793,7 @@ int launch_iteration(Cg<T>& c, int32_t k, hipStream_t s) {
         // stores z and the (r, z) partials; K3 reads z
         hipLaunchKernelGGL((cg_update_r<T, false>), gv, bv, 0, s, c.n, k, c.g_spmv, c.r, c.q, c.dinv, c.part, c.st);
         RP_HIP_TRY(hipGetLastError());
-        RP_TRY(amg_apply<T>(c.plan, c.r, c.z, c.part, c.g_rz, false, &c.st->kk, s));
+        RP_TRY(amg_apply<T>(c.plan, c.r, c.z, c.part, c.g_rz, false, &c.st->kk, s, c.amg_ordered));
         hipLaunchKernelGGL((cg_update_xp<T, true>), gv, bv, 0, s, c.n, k, c.g_rz, c.g_vec, 0, c.r, c.dinv, c.z, c.x,
                            c.p, c.part, c.st);
     } else if (c.bj_minv) {
@@ -915,8 +916,9 @@ void use_block_jacobi(Cg<T>& c, const rp_plan* p, const T* minv, T* z) {
 
 // the multigrid V-cycle for this solve (the hierarchy is current)
 template <typename T>
-void use_amg(Cg<T>& c, T* z) {
+void use_amg(Cg<T>& c, T* z, bool ordered) {
     c.amg = true;
+    c.amg_ordered = ordered;
     c.z = z;
     c.g_rz = c.g_spmv;
 }
@@ -964,8 +966,8 @@ int solve_fp64(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, r
         RP_TRY(bj_prepare(p, o.block_size, s));
         use_block_jacobi(c, p, p->d_bj_minv64, p->d_z);
     } else if (o.precond == RP_PRECOND_AMG) {
-        RP_TRY(amg_prepare(p, false, s));
-        use_amg(c, p->d_z);
+        RP_TRY(amg_prepare(p, false, s, ordered));
+        use_amg(c, p->d_z, ordered);
     }
     const double tol2 = o.tol * o.tol;
     const int chunk = std::max(1, o.check_every);
@@ -1039,8 +1041,8 @@ int solve_mixed(rp_plan* p, const double* b, double* x, const rp_solve_opts& o, 
         RP_TRY(bj_prepare(p, o.block_size, s));
         use_block_jacobi(in, p, p->d_bj_minv32, p->d_z32);
     } else if (o.precond == RP_PRECOND_AMG) {
-        RP_TRY(amg_prepare(p, true, s));
-        use_amg(in, p->d_z32);
+        RP_TRY(amg_prepare(p, true, s, ordered));
+        use_amg(in, p->d_z32, ordered);
     }
     const int chunk = std::max(1, o.check_every);
 

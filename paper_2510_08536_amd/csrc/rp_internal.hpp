@@ -278,6 +278,7 @@ struct rp_plan {
     uint32_t* d_loop_bar = nullptr;    // abort word and per-block barrier flags of the CG loop (cg_loop.hip)
 
     rp::AmgHier* amg = nullptr;        // multigrid hierarchy (RP_PRECOND_AMG), built on first use
+    rp::AmgHier* amg_ro = nullptr;     // the same on the solve-order copy
 
     // captured CG iteration chunks (rp_solve_opts.graph), [0] FP64, [1] FP32
     hipStream_t capture_stream = nullptr;
@@ -363,16 +364,18 @@ int bj_prepare(rp_plan* p, int32_t bs, hipStream_t s);
 // the preconditioned-residual vectors d_z / d_z32
 int alloc_z(rp_plan* p);
 // amg.hip
-// hierarchy from the current values (aggregates, patterns, coarse values)
-int amg_setup(rp_plan* p, hipStream_t s);
+// hierarchy from the current values (aggregates, patterns, coarse values);
+// ordered: on the solve-order copy instead of the fused pattern
+int amg_setup(rp_plan* p, hipStream_t s, bool ordered = false);
 // hierarchy present and its values current; V-cycle vectors of one precision
-int amg_prepare(rp_plan* p, bool fp32, hipStream_t s);
+int amg_prepare(rp_plan* p, bool fp32, hipStream_t s, bool ordered = false);
 void amg_free(rp_plan* p);
-// y = V-cycle(r) on the level-0 system (fused order).  part != null: partials
-// of (r, y) -> PART_RZ (and, rr, of (r, r) -> PART_RR), n_part of them.
-// gate != null: every kernel returns when *gate < 0.
+// y = V-cycle(r) on the level-0 system.  part != null: partials of (r, y) ->
+// PART_RZ (and, rr, of (r, r) -> PART_RR), n_part of them.  gate != null:
+// every kernel returns when *gate < 0.
 template <typename T>
-int amg_apply(rp_plan* p, const T* r, T* y, T* part, int32_t n_part, bool rr, const int32_t* gate, hipStream_t s);
+int amg_apply(rp_plan* p, const T* r, T* y, T* part, int32_t n_part, bool rr, const int32_t* gate, hipStream_t s,
+              bool ordered = false);
 // order.hip
 // reverse Cuthill-McKee order of a structurally symmetric pattern: perm[k] = row at position k
 std::vector<int32_t> rcm_order(int32_t n, const int32_t* row_ptr, const int32_t* col);

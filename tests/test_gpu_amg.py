@@ -164,7 +164,7 @@ def test_amg_rejections():
     assert e.value.code == RP_ERR_UNSUPPORTED
     plan.set_solve_order("rcm")
     with pytest.raises(RpError) as e:
-        plan.solve(b, precond="amg")
+        plan.solve(b, precond="block_jacobi", block_size=4)
     assert e.value.code == RP_ERR_UNSUPPORTED
     plan.set_solve_order("fused")
     plan.amg_setup()
@@ -201,4 +201,29 @@ def test_amg_large_hierarchy_bit_exact_and_solve():
     print(f"c4: {info['iters']} it (oracle {it_or}), rel.res {rr:.2e}, err {err:.2e}, levels {h.n_levels}")
     assert info["status"] == 0 and rr <= 1e-8 and err <= 1e-6
     assert abs(info["iters"] - it_or) <= max(2, int(0.02 * it_or))
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_amg_on_the_solve_order(precision):
+    """Scrambled numbering: the multigrid built on the reverse Cuthill-McKee
+    copy (its own hierarchy), b and x in fused order; the answer meets the
+    oracle's bars against the oracle's solution of the fused system, and a
+    value update refreshes that hierarchy too."""
+    w = synth.small((24, 22, 20), ("rcb", 9), kappa=(1e-3, 1.0), seed=28, scramble=True, timesteps=2)
+    m, v0, plan = _setup(w, 0)
+    plan.set_solve_order("rcm")
+    b = w.rhs()
+    for t, v in ((0, v0), (1, None)):
+        if t == 1:
+            _, _, v, *_ = oracle_system(w, 1)
+            update(plan, share_values(w, 1))
+        x_or, st, it_or, *_ = oracle.pcg(m, v, b, tol=1e-12)
+        assert st == 0
+        x, info = plan.solve(dev_tensor(b), tol=1e-8, precision=precision, precond="amg")
+        xh = x.cpu().numpy()
+        rr = oracle.true_relres(m, v, b, xh)
+        err = np.linalg.norm(xh - x_or) / np.linalg.norm(x_or)
+        print(f"rcm t={t} {precision}: {info['iters']} it, rel.res {rr:.2e}, err {err:.2e}")
+        assert info["status"] == 0 and info["restarts"] == 0 and rr <= 1e-8 and err <= 1e-6, (info, rr, err)
     plan.close()
