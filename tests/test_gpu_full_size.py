@@ -116,8 +116,9 @@ def _against_reference(name, plan, m, val64, b, runs):
 
 @pytest.mark.timeout(900)
 def test_c3_fp64_and_mixed():
-    """256^3, 64 ranks, kappa in [1e-3, 1]: FP64, mixed refinement and
-    residual replacement against the oracle's 1e-12 solution."""
+    """256^3, 64 ranks, kappa in [1e-3, 1]: FP64, mixed refinement, residual
+    replacement, block-Jacobi and multigrid against the oracle's 1e-12
+    solution; the multigrid hierarchy and one V-cycle bit-exact."""
     w = synth.build("c3")
     m, vals, want = _system(w)
     plan = make_plan(w)
@@ -132,7 +133,19 @@ def test_c3_fp64_and_mixed():
                        [("fp64", dict(precision="fp64")), ("mixed", dict(precision="mixed")),
                         ("mixed_rr", dict(precision="mixed_rr")),
                         ("fp64 block-Jacobi 4", dict(precision="fp64", precond="block_jacobi", block_size=4)),
-                        ("mixed block-Jacobi 4", dict(precision="mixed", precond="block_jacobi", block_size=4))])
+                        ("mixed block-Jacobi 4", dict(precision="mixed", precond="block_jacobi", block_size=4)),
+                        ("fp64 multigrid", dict(precision="fp64", precond="amg")),
+                        ("mixed multigrid", dict(precision="mixed", precond="amg"))])
+    # the multigrid hierarchy those solves built, and one V-cycle, bit for
+    # bit against the oracle's at this size
+    from test_gpu_amg import _compare_hierarchy
+    h = oracle.AmgHierarchy(m, val64)
+    _compare_hierarchy(plan, h, "c3")
+    r = np.random.default_rng(9).uniform(-1, 1, m.n_rows)
+    assert_bits_equal(plan.amg_apply(dev_tensor(r)).cpu().numpy(), h.vcycle(r), "c3 V-cycle")
+    print(f"c3 multigrid: {h.n_levels} levels, hierarchy and one V-cycle bit-exact")
+    del h
+    gc.collect()
     # the same plan refreshed with non-symmetric momentum-type values:
     # update bit-exact, BiCGStab to a true residual of 1e-8
     del val64
@@ -245,5 +258,7 @@ def test_c5_solves_against_reference(order):
             ("mixed_rr", dict(precision="mixed_rr"))]
     if order == "fused":
         runs.append(("fp64 block-Jacobi 4", dict(precision="fp64", precond="block_jacobi", block_size=4)))
+    runs += [("fp64 multigrid", dict(precision="fp64", precond="amg")),
+             ("mixed multigrid", dict(precision="mixed", precond="amg"))]
     _against_reference("c5", plan, m, want[0], w.rhs(), runs)
     plan.close()
