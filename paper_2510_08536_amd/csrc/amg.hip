@@ -347,7 +347,24 @@ __device__ __forceinline__ T chunk_row_sum(const int32_t* __restrict__ row_ptr, 
     const int32_t e0 = row_ptr[r0], e1 = row_ptr[r0 + nr];
     T s = T(0);
     if (e1 - e0 <= AMG_LCAP) {
-        for (int32_t e = e0 + t; e < e1; e += AB) prod[e - e0] = val[e] * x[col[e]];
+        // all of the thread's (at most AMG_LCAP / AB) column, value and x
+        // loads in flight together, then the products
+        constexpr int U = AMG_LCAP / AB;
+        int32_t cv[U];
+        T vv[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t e = e0 + t + u * AB;
+            cv[u] = e < e1 ? col[e] : 0;
+            vv[u] = e < e1 ? val[e] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = (e0 + t + u * AB < e1) ? x[cv[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t e = e0 + t + u * AB;
+            if (e < e1) prod[e - e0] = vv[u] * xv[u];
+        }
         __syncthreads();
         if (t < nr)
             for (int32_t e = row_ptr[r0 + t]; e < row_ptr[r0 + t + 1]; ++e) s += prod[e - e0];
@@ -415,9 +432,23 @@ amg_restrict(int32_t nc, const int32_t* __restrict__ mem_ptr, const int32_t* __r
              const T* __restrict__ v, T* __restrict__ rc, const int32_t* gate) {
 #pragma clang fp contract(off)
     if (gate && *gate < 0) return;
+    constexpr int M = 8;   // aggregates up to M rows: every load issued first
     for (int32_t I = blockIdx.x * AB + threadIdx.x; I < nc; I += gridDim.x * AB) {
+        const int32_t a0 = mem_ptr[I], a1 = mem_ptr[I + 1];
         T s = T(0);
-        for (int32_t m = mem_ptr[I]; m < mem_ptr[I + 1]; ++m) s += v[mem[m]];
+        if (a1 - a0 <= M) {
+            int32_t mi[M];
+            T vv[M];
+#pragma unroll
+            for (int u = 0; u < M; ++u) mi[u] = a0 + u < a1 ? mem[a0 + u] : 0;
+#pragma unroll
+            for (int u = 0; u < M; ++u) vv[u] = a0 + u < a1 ? v[mi[u]] : T(0);
+#pragma unroll
+            for (int u = 0; u < M; ++u)
+                if (a0 + u < a1) s += vv[u];
+        } else {
+            for (int32_t m = a0; m < a1; ++m) s += v[mem[m]];
+        }
         rc[I] = s;
     }
 }
