@@ -76,7 +76,8 @@ extern "C" {
                                      every block inside one CPU rank (CG only) */
 #define RP_BJ_MAX_BLOCK 8
 #define RP_PRECOND_AMG 2          /* M^-1 = one V-cycle of aggregation multigrid on the
-                                     whole fused system (CG only; rp_plan_amg_setup) */
+                                     whole system, fused or solve order (CG only;
+                                     rp_plan_amg_setup) */
 #define RP_AMG_OMEGA 0.8          /* damping of the multigrid's Jacobi sweeps */
 #define RP_AMG_COARSE_MAX 64      /* rows of the coarsest level at most (dense inverse) */
 
@@ -421,8 +422,12 @@ int rp_plan_block_jacobi(rp_plan* plan, int32_t block_size, int64_t* n_blocks, i
  *
  * The first solve with RP_PRECOND_AMG builds the hierarchy from the values at
  * hand; later value updates keep the aggregates and patterns and refresh the
- * coarse values (steps 4-5) at the next such solve.  rp_plan_amg_setup
- * rebuilds it from the current values (synchronises on stream). */
+ * coarse values (steps 4-5) at the next such solve.  With the solve order
+ * (rp_plan_set_solve_order) the plan keeps a second hierarchy, built the
+ * same way on the renumbered system.  rp_plan_amg_setup rebuilds the fused
+ * hierarchy from the current values and drops the solve-order one, which
+ * the next multigrid solve in solve order rebuilds (synchronises on
+ * stream). */
 int rp_plan_amg_setup(rp_plan* plan, void* stream);
 
 /* Number of levels of the hierarchy (0 before the first setup). */

@@ -844,6 +844,9 @@ int amg_setup(rp_plan* p, hipStream_t s, bool ordered) {
     }
     AmgHier*& hp = hier(p, ordered);
     free_hier(hp);
+    // a fused-order rebuild also retires the solve-order hierarchy: the next
+    // multigrid solve in solve order builds it from the values then current
+    if (!ordered) free_hier(p->amg_ro);
     hp = new AmgHier();
     AmgHier& h = *hp;
     const Src q = source(p, ordered);

@@ -226,4 +226,10 @@ def test_amg_on_the_solve_order(precision):
         err = np.linalg.norm(xh - x_or) / np.linalg.norm(x_or)
         print(f"rcm t={t} {precision}: {info['iters']} it, rel.res {rr:.2e}, err {err:.2e}")
         assert info["status"] == 0 and info["restarts"] == 0 and rr <= 1e-8 and err <= 1e-6, (info, rr, err)
+    # an explicit rebuild (fused hierarchy) retires the solve-order one; the
+    # next solve in solve order builds it again from the current values
+    plan.amg_setup()
+    x, info = plan.solve(dev_tensor(b), tol=1e-8, precision=precision, precond="amg")
+    rr = oracle.true_relres(m, v, b, x.cpu().numpy())
+    assert info["status"] == 0 and rr <= 1e-8, (info, rr)
     plan.close()
