@@ -320,52 +320,42 @@ amg_resid(int32_t n, SpmvIdx ix, const T* __restrict__ val, const T* __restrict_
     }
 }
 
-// Coarse levels (plain CSR, 10 to 30 entries per row): blocks of AMG_CHUNK
-// consecutive rows.  The block's threads form the chunk's products val * x
-// together (coalesced over the entries) into LDS, then one thread per row
-// sums its row's products in column order from 0: the same single roundings
-// as the serial row sum.  A chunk with more than AMG_LCAP entries is summed
-// straight from memory, one thread per row.
-constexpr int AMG_CHUNK = 128;
-constexpr int AMG_LCAP = 4096;
+// Coarse levels (plain CSR, 10 to 30 entries per row): one wavefront per
+// block, chunks of CR consecutive rows (64, or 32 on levels with more than
+// 12 entries per row).  The wave forms the chunk's products val * x together
+// (coalesced over the entries, every load of a lane issued before the first
+// product) into LDS, then each lane sums its row's products in column order
+// from 0: the same single roundings as the serial row sum.  A chunk with
+// more than WCAP entries is summed straight from memory, a lane per row.
+constexpr int WB = 64;            // threads per block: one wavefront
+constexpr int WCAP = 1024;        // staged products per chunk
+constexpr int WU = WCAP / WB;     // loads per lane
 
 template <typename T>
-__device__ __forceinline__ bool chunk_rows(int32_t c, int32_t n, int32_t& r0, int32_t& nr) {
-    r0 = c * AMG_CHUNK;
-    nr = min(AMG_CHUNK, n - r0);
-    return nr > 0;
-}
-
-// row sum s_i = (A x)_i of the chunk's row r0 + threadIdx.x (valid for
-// threadIdx.x < nr); prod: AMG_LCAP elements of LDS
-template <typename T>
-__device__ __forceinline__ T chunk_row_sum(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                                           const T* __restrict__ val, const T* __restrict__ x, int32_t r0,
-                                           int32_t nr, T* prod) {
+__device__ __forceinline__ T wave_row_sum(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                          const T* __restrict__ val, const T* __restrict__ x, int32_t r0,
+                                          int32_t nr, T* prod) {
 #pragma clang fp contract(off)
     const int32_t t = threadIdx.x;
     const int32_t e0 = row_ptr[r0], e1 = row_ptr[r0 + nr];
     T s = T(0);
-    if (e1 - e0 <= AMG_LCAP) {
-        // all of the thread's (at most AMG_LCAP / AB) column, value and x
-        // loads in flight together, then the products
-        constexpr int U = AMG_LCAP / AB;
-        int32_t cv[U];
-        T vv[U], xv[U];
+    if (e1 - e0 <= WCAP) {
+        int32_t cv[WU];
+        T vv[WU], xv[WU];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t e = e0 + t + u * AB;
+        for (int u = 0; u < WU; ++u) {
+            const int32_t e = e0 + t + u * WB;
             cv[u] = e < e1 ? col[e] : 0;
             vv[u] = e < e1 ? val[e] : T(0);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = (e0 + t + u * AB < e1) ? x[cv[u]] : T(0);
+        for (int u = 0; u < WU; ++u) xv[u] = (e0 + t + u * WB < e1) ? x[cv[u]] : T(0);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t e = e0 + t + u * AB;
+        for (int u = 0; u < WU; ++u) {
+            const int32_t e = e0 + t + u * WB;
             if (e < e1) prod[e - e0] = vv[u] * xv[u];
         }
-        __syncthreads();
+        __syncthreads();   // one wave: orders its LDS writes before the reads
         if (t < nr)
             for (int32_t e = row_ptr[r0 + t]; e < row_ptr[r0 + t + 1]; ++e) s += prod[e - e0];
         __syncthreads();   // prod is refilled by the next chunk
@@ -376,19 +366,18 @@ __device__ __forceinline__ T chunk_row_sum(const int32_t* __restrict__ row_ptr, 
 }
 
 // t = r - A x on a coarse level
-template <typename T>
-__global__ void __launch_bounds__(AB)
+template <typename T, int CR>
+__global__ void __launch_bounds__(WB)
 amg_csr_resid(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
               const T* __restrict__ val, const T* __restrict__ x, const T* __restrict__ r, T* __restrict__ t,
               const int32_t* gate) {
 #pragma clang fp contract(off)
-    __shared__ T prod[AMG_LCAP];
+    __shared__ T prod[WCAP];
     if (gate && *gate < 0) return;
-    const int32_t nch = (n + AMG_CHUNK - 1) / AMG_CHUNK;
+    const int32_t nch = (n + CR - 1) / CR;
     for (int32_t c = xcd_block(); c < nch; c += gridDim.x) {
-        int32_t r0, nr;
-        chunk_rows<T>(c, n, r0, nr);
-        const T s = chunk_row_sum<T>(row_ptr, col, val, x, r0, nr, prod);
+        const int32_t r0 = c * CR, nr = min(CR, n - r0);
+        const T s = wave_row_sum<T>(row_ptr, col, val, x, r0, nr, prod);
         if ((int32_t)threadIdx.x < nr) {
             const int32_t i = r0 + threadIdx.x;
             t[i] = r[i] - s;
@@ -397,19 +386,18 @@ amg_csr_resid(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __r
 }
 
 // y = x + omega (dinv (r - A x)) on a coarse level
-template <typename T>
-__global__ void __launch_bounds__(AB)
+template <typename T, int CR>
+__global__ void __launch_bounds__(WB)
 amg_csr_post(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
              const T* __restrict__ val, const T* __restrict__ x, const T* __restrict__ r,
              const T* __restrict__ dinv, T omega, T* __restrict__ y, const int32_t* gate) {
 #pragma clang fp contract(off)
-    __shared__ T prod[AMG_LCAP];
+    __shared__ T prod[WCAP];
     if (gate && *gate < 0) return;
-    const int32_t nch = (n + AMG_CHUNK - 1) / AMG_CHUNK;
+    const int32_t nch = (n + CR - 1) / CR;
     for (int32_t c = xcd_block(); c < nch; c += gridDim.x) {
-        int32_t r0, nr;
-        chunk_rows<T>(c, n, r0, nr);
-        const T s = chunk_row_sum<T>(row_ptr, col, val, x, r0, nr, prod);
+        const int32_t r0 = c * CR, nr = min(CR, n - r0);
+        const T s = wave_row_sum<T>(row_ptr, col, val, x, r0, nr, prod);
         if ((int32_t)threadIdx.x < nr) {
             const int32_t i = r0 + threadIdx.x;
             y[i] = x[i] + omega * (dinv[i] * (r[i] - s));
@@ -417,12 +405,15 @@ amg_csr_post(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __re
     }
 }
 
+// chunk rows of a level: 64, or 32 where rows average more than 12 entries
+int chunk_rows(const AmgLevel& L) { return L.nnz > 12 * L.n ? 32 : 64; }
+
 // grid of the chunked kernels: a multiple of 8 (xcd_block), one chunk per
-// block up to 2048 blocks
-int chunk_grid(int64_t n) {
-    int64_t g = (n + AMG_CHUNK - 1) / AMG_CHUNK;
+// block up to 16384 blocks
+int chunk_grid(int64_t n, int cr) {
+    int64_t g = (n + cr - 1) / cr;
     g = ((g + N_XCD - 1) / N_XCD) * N_XCD;
-    return (int)std::max<int64_t>(N_XCD, std::min<int64_t>(g, 2048));
+    return (int)std::max<int64_t>(N_XCD, std::min<int64_t>(g, 16384));
 }
 
 // rc[I] = sum of v over the members of aggregate I, ascending
@@ -640,13 +631,16 @@ int vcycle(AmgHier& h, const Src& q, int32_t l, const T* r, T* y, T* part, int32
     const T* val = l == 0 ? Prec<T>::val0(q) : Prec<T>::val(L);
     const T* dinv = l == 0 ? Prec<T>::dinv0(q) : Prec<T>::dinv(L);
     const SpmvIdx ix = level_idx(q, L, l);
-    const int gs = spmv_grid(n), gc = chunk_grid(n);
+    const int gs = spmv_grid(n), cr = chunk_rows(L), gc = chunk_grid(n, cr);
     hipLaunchKernelGGL(amg_pre<T>, dim3(grid_of(n)), dim3(AB), 0, s, n, r, dinv, v[1], omega, gate);
     if (l == 0)
         hipLaunchKernelGGL(amg_resid<T>, dim3(gs), dim3(SPMV_BLOCK), 0, s, n, ix, val, v[1], r, v[2], gate);
+    else if (cr == 64)
+        hipLaunchKernelGGL((amg_csr_resid<T, 64>), dim3(gc), dim3(WB), 0, s, n, L.row_ptr, L.col, val, v[1], r,
+                           v[2], gate);
     else
-        hipLaunchKernelGGL(amg_csr_resid<T>, dim3(gc), dim3(AB), 0, s, n, L.row_ptr, L.col, val, v[1], r, v[2],
-                           gate);
+        hipLaunchKernelGGL((amg_csr_resid<T, 32>), dim3(gc), dim3(WB), 0, s, n, L.row_ptr, L.col, val, v[1], r,
+                           v[2], gate);
     hipLaunchKernelGGL(amg_restrict<T>, dim3(grid_of(nc)), dim3(AB), 0, s, nc, L.mem_ptr, L.mem, v[2], cv[0], gate);
     RP_HIP_TRY(hipGetLastError());
     RP_TRY(vcycle<T>(h, q, l + 1, cv[0], cv[3], nullptr, 0, false, gate, s));
@@ -657,9 +651,12 @@ int vcycle(AmgHier& h, const Src& q, int32_t l, const T* r, T* y, T* part, int32
     if (want && rr) RP_LAUNCH(true, true);
     else if (want) RP_LAUNCH(true, false);
     else if (l == 0) RP_LAUNCH(false, false);
+    else if (cr == 64)
+        hipLaunchKernelGGL((amg_csr_post<T, 64>), dim3(gc), dim3(WB), 0, s, n, L.row_ptr, L.col, val, v[1], r, dinv,
+                           omega, y, gate);
     else
-        hipLaunchKernelGGL(amg_csr_post<T>, dim3(gc), dim3(AB), 0, s, n, L.row_ptr, L.col, val, v[1], r, dinv, omega,
-                           y, gate);
+        hipLaunchKernelGGL((amg_csr_post<T, 32>), dim3(gc), dim3(WB), 0, s, n, L.row_ptr, L.col, val, v[1], r, dinv,
+                           omega, y, gate);
 #undef RP_LAUNCH
     RP_HIP_TRY(hipGetLastError());
     return RP_OK;
