@@ -293,6 +293,9 @@ def main():
                                                                           block_size=4)),
                                             ("amg", dict(precision="fp64", precond="amg")),
                                             ("mixed_amg", dict(precision="mixed", precond="amg")))
+    if a.solve_order != "fused":
+        # block-Jacobi blocks are runs of fused rows: not in the solve order
+        legs = tuple(lg for lg in legs if lg[1].get("precond") != "block_jacobi")
     amg_info = None
     if legs:
         # multigrid hierarchy of the last step's system, built once (the legs
