@@ -130,7 +130,8 @@ def main():
             pool_err = f"{type(e).__name__}: {e}"
 
     import torch
-    from paper_2510_08536_amd import Plan, default_opts, RP_KERNEL_SPMV64, RP_KERNEL_SPMV32, RP_KERNEL_SCATTER
+    from paper_2510_08536_amd import (Plan, default_opts, RP_KERNEL_SPMV64, RP_KERNEL_SPMV32, RP_KERNEL_SCATTER,
+                                      RP_LOOP_AUTO, RP_LOOP_COOPERATIVE, RP_LOOP_THREE, RP_LOOP_TWO_MAX_ROWS)
 
     assert torch.cuda.is_available()
     dev = torch.device("cuda:0")
@@ -335,12 +336,16 @@ def main():
         plan.update(*steps_vals[n_steps_total - 1])
         bj["amg_hierarchy"] = amg_info
     print(f"[bench] preconditioners: {bj}", flush=True)
-    # CG iterations in one cooperative launch against the three-kernel
-    # iteration (kernel timing off in both): per-iteration time, on systems
-    # of up to 2^20 rows
+    # launches per CG iteration (kernel timing off in all): three, two (the
+    # x and p update fused with the next SpMV; systems of at most
+    # RP_LOOP_TWO_MAX_ROWS rows) and one cooperative launch; per-iteration
+    # time, on systems of up to 2^20 rows
     loop = {}
+    forms = [(RP_LOOP_THREE, "three_kernel"), (RP_LOOP_COOPERATIVE, "single_launch")]
+    if n <= RP_LOOP_TWO_MAX_ROWS:
+        forms.insert(1, (RP_LOOP_AUTO, "two_launch"))
     for prec in (() if a.no_loop_legs or n > (1 << 20) else ("fp64", "mixed")):
-        for fl, label in ((0, "three_kernel"), (1, "single_launch")):
+        for fl, label in forms:
             kw = dict(tol=1e-8, x0_zero=1, precision=prec, fused_loop=fl)
             plan.solve(b, opts=default_opts(**kw))
             ts, its = [], []
@@ -355,8 +360,9 @@ def main():
             ms, it_ = float(np.median(ts)), int(np.median(its))
             loop[f"{prec}_{label}"] = {"ms_per_solve": round(ms, 3), "iters": it_,
                                        "us_per_iter": round(1e3 * ms / max(it_, 1), 2)}
-        loop[f"{prec}_single_launch"]["speedup"] = round(loop[f"{prec}_three_kernel"]["ms_per_solve"]
-                                                         / loop[f"{prec}_single_launch"]["ms_per_solve"], 3)
+        for _, label in forms[1:]:
+            loop[f"{prec}_{label}"]["speedup"] = round(loop[f"{prec}_three_kernel"]["ms_per_solve"]
+                                                       / loop[f"{prec}_{label}"]["ms_per_solve"], 3)
     print(f"[bench] cg loop: {loop}", flush=True)
 
     el = lambda e_a, e_b: e_a.elapsed_time(e_b)

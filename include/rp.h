@@ -81,6 +81,13 @@ extern "C" {
 #define RP_AMG_OMEGA 0.8          /* damping of the multigrid's Jacobi sweeps */
 #define RP_AMG_COARSE_MAX 64      /* rows of the coarsest level at most (dense inverse) */
 
+/* ---- launches per Jacobi-PCG iteration (rp_solve_opts.fused_loop) ------- */
+#define RP_LOOP_AUTO 0            /* two launches on systems of at most RP_LOOP_TWO_MAX_ROWS
+                                     rows, three on larger ones */
+#define RP_LOOP_COOPERATIVE 1     /* all iterations in one cooperative launch */
+#define RP_LOOP_THREE 2           /* three launches (SpMV; r update; x and p update) */
+#define RP_LOOP_TWO_MAX_ROWS 262144
+
 /* ---- Krylov methods ------------------------------------------------------ */
 #define RP_CG 0                   /* Jacobi-PCG, symmetric positive definite A (the pressure
                                      system, Sec. 4) */
@@ -132,15 +139,23 @@ typedef struct rp_solve_opts {
     int32_t precond;         /* RP_PRECOND_JACOBI (default), RP_PRECOND_BLOCK_JACOBI or RP_PRECOND_AMG
                                 (RP_CG, fused solve order; FP64 and both mixed forms) */
     int32_t block_size;      /* block-Jacobi rows per block, 1..RP_BJ_MAX_BLOCK (default 4) */
-    int32_t fused_loop;      /* RP_CG with Jacobi: 1 runs the iterations in one cooperative
-                                launch (the three phases of an iteration separated by
-                                grid-wide barriers instead of kernel boundaries; same
-                                arithmetic, partial sums over a smaller grid), 0 (default)
-                                one launch per phase.  Ignored (one launch per phase) with
-                                kernel timing, graph replay, block-Jacobi, or where the
-                                device cannot launch the grid cooperatively.  On MI355X the
-                                single launch measured slower at every size tried: each
-                                barrier writes back and invalidates a die's L2 per block. */
+    int32_t fused_loop;      /* RP_CG with Jacobi, how an iteration is launched.
+                                RP_LOOP_THREE: one launch per phase (SpMV with (p, q);
+                                r update with (r, z), (r, r); x and p update).
+                                RP_LOOP_AUTO (default): the same on systems above
+                                RP_LOOP_TWO_MAX_ROWS rows; on smaller ones two launches, the
+                                x and p update of iteration k fused with the SpMV of k + 1
+                                (each row forms the new p of its columns itself), with
+                                results bit-identical to RP_LOOP_THREE.
+                                RP_LOOP_COOPERATIVE: all iterations in one cooperative
+                                launch (the phases separated by grid-wide barriers; same
+                                arithmetic, partial sums over a smaller grid); on MI355X it
+                                measured slower at every size tried, since each barrier
+                                writes back and invalidates a die's L2 per block.
+                                Kernel timing, graph replay, block-Jacobi and the
+                                multigrid always take three launches per iteration, as
+                                does RP_LOOP_COOPERATIVE where the device cannot launch
+                                the grid cooperatively. */
 } rp_solve_opts;
 
 typedef struct rp_solve_info {

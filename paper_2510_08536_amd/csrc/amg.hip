@@ -574,19 +574,15 @@ int alloc_vectors(AmgHier& h) {
     for (int32_t l = 0; l < h.n_levels; ++l) {
         AmgLevel& L = h.lev[l];
         T** v = Prec<T>::vec(L);
-        if (v[0] || v[1]) continue;
         const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(L.n, 1);
         // in and out below level 0 (level 0 uses the solve's vectors); x and t
-        // on smoothed levels
+        // on smoothed levels.  Each one is allocated once, so a call after a
+        // failed one completes the set.
         const bool last = l == h.n_levels - 1;
         const bool smooth = !last && l % 2 == 0;
-        if (l > 0) {
-            RP_HIP_TRY(hipMalloc(&v[0], bytes));
-            RP_HIP_TRY(hipMalloc(&v[3], bytes));
-        }
-        if (smooth) {
-            RP_HIP_TRY(hipMalloc(&v[1], bytes));
-            RP_HIP_TRY(hipMalloc(&v[2], bytes));
+        for (int k = 0; k < 4; ++k) {
+            const bool need = (k == 0 || k == 3) ? l > 0 : smooth;
+            if (need && !v[k]) RP_HIP_TRY(hipMalloc(&v[k], bytes));
         }
     }
     return RP_OK;
@@ -820,7 +816,8 @@ int refresh(AmgHier& h, const Src& q, int64_t version, hipStream_t s) {
 void free_hier(AmgHier*& hp) {
     if (!hp) return;
     AmgHier& h = *hp;
-    for (int32_t l = 0; l < h.n_levels; ++l) free_level(h.lev[l]);
+    // every level: a failed coarsening leaves arrays on the level it was building
+    for (int32_t l = 0; l < AMG_MAX_LEVELS; ++l) free_level(h.lev[l]);
     for (void* a : {(void*)h.cinv64, (void*)h.cinv32, (void*)h.cwork, (void*)h.flag})
         if (a) (void)hipFree(a);
     delete hp;
@@ -869,7 +866,9 @@ int amg_setup(rp_plan* p, hipStream_t s, bool ordered) {
         const double* fine = h.n_levels == 2 ? q.val64 : L.val64;
         hipLaunchKernelGGL(amg_gvals, dim3(grid_of(C.nnz)), dim3(AB), 0, s, (int32_t)C.nnz, L.cptr, L.cpos, fine,
                            C.val64, C.val32);
-        RP_HIP_TRY(hipGetLastError());
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return fail((set_error("launching amg_gvals failed: %s", hipGetErrorString(e)), RP_ERR_HIP));
     }
     const int64_t nL = h.lev[h.n_levels - 1].n;
     h.cinv64 = dalloc<double>(nL * nL);

@@ -550,7 +550,7 @@ void rp_solve_opts_default(rp_solve_opts* o) {
     o->graph = 0;
     o->precond = RP_PRECOND_JACOBI;
     o->block_size = 4;
-    o->fused_loop = 0;
+    o->fused_loop = RP_LOOP_AUTO;
 }
 
 int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, rp_solve_info* info,
@@ -574,7 +574,8 @@ int rp_solve(rp_plan* p, const double* b, double* x, const rp_solve_opts* opts, 
     RP_CHECK(o.method == RP_CG || o.precision == RP_FP64, RP_ERR_UNSUPPORTED, "BiCGStab runs in FP64 only");
     RP_CHECK(o.transpose == 0 || o.transpose == 1, RP_ERR_ARG, "transpose must be 0 or 1");
     RP_CHECK(o.graph == 0 || o.graph == 1, RP_ERR_ARG, "graph must be 0 or 1");
-    RP_CHECK(o.fused_loop == 0 || o.fused_loop == 1, RP_ERR_ARG, "fused_loop must be 0 or 1");
+    RP_CHECK(o.fused_loop == RP_LOOP_AUTO || o.fused_loop == RP_LOOP_COOPERATIVE || o.fused_loop == RP_LOOP_THREE,
+             RP_ERR_ARG, "fused_loop must be RP_LOOP_AUTO, RP_LOOP_COOPERATIVE or RP_LOOP_THREE");
     RP_CHECK(o.precond == RP_PRECOND_JACOBI || o.precond == RP_PRECOND_BLOCK_JACOBI || o.precond == RP_PRECOND_AMG,
              RP_ERR_ARG, "precond must be RP_PRECOND_JACOBI, RP_PRECOND_BLOCK_JACOBI or RP_PRECOND_AMG");
     RP_CHECK(o.precond == RP_PRECOND_JACOBI || (o.block_size >= 1 && o.block_size <= RP_BJ_MAX_BLOCK), RP_ERR_ARG,

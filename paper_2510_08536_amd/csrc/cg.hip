@@ -7,6 +7,9 @@
 //                                    partials of (r, M^-1 r) and (r, r)
 //   K3  x += alpha p; stop tests, beta = rz_{k+1} / rz_k, p = M^-1 r + beta p
 // (x moves in K3, which reads p anyway: one pass over p less per iteration)
+// Small systems run K3 of iteration k and K1 of iteration k + 1 as one
+// kernel (cg_update_xp_spmv), two launches per iteration with the same
+// results bit for bit.
 // Each kernel starts by adding up the previous kernel's per-block partials
 // (every block the same sum, in index order), so reductions need no atomics,
 // no fences and no extra launches, and reruns are bit-identical.  The
@@ -32,6 +35,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <utility>
 
 #include "spmv.hpp"
 
@@ -358,6 +362,102 @@ cg_update_xp(int32_t n, int32_t k_arg, int32_t g_rz, int32_t g_rr, int32_t resum
     }
 }
 
+// K3 of iteration k fused with K1 of iteration k + 1 (systems of at most
+// RP_LOOP_TWO_MAX_ROWS rows, Jacobi M, rows read as plain CSR).  The stop
+// tests and x += alpha p_k are K3's.  Unless stopping, p_{k+1} = M^-1 r +
+// beta p_k of a row is formed wherever it is needed: once by the row itself,
+// which stores it into pn, and again, by the same operations, by every row
+// coupled to it, so q = A p_{k+1} and the (p, q) partials come out of this
+// launch.  p_k (po) and p_{k+1} (pn) are separate buffers; on a stop pn
+// receives p_k, so after this kernel ran the current direction is in pn.
+// Rows go to blocks as in K1 and each row sums its products in column order
+// from 0, so q and the partials are K1's bit for bit.  Gated on kk like K3.
+template <typename T>
+__global__ void __launch_bounds__(SPMV_BLOCK)
+cg_update_xp_spmv(int32_t n, int32_t k, int32_t g_vec, const int32_t* __restrict__ row_ptr,
+                  const int32_t* __restrict__ col, const T* __restrict__ val, const T* __restrict__ r,
+                  const T* __restrict__ dinv, const T* __restrict__ po, T* __restrict__ pn, T* __restrict__ x,
+                  T* __restrict__ q, T* __restrict__ part, CgState<T>* st) {
+#pragma clang fp contract(off)
+    if (st->kk != k) return;
+    __shared__ T red[SPMV_BLOCK / 64];
+    const T rz = sum_partials_all<T, SPMV_BLOCK>(part + PART_RZ, g_vec, red);
+    const T rr = sum_partials_all<T, SPMV_BLOCK>(part + PART_RR, g_vec, red);
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    int32_t stop = CG_RUNNING;
+    if (rr <= st->thresh) stop = CG_CONVERGED;
+    else if (!(rz > T(0)) || !isfinite(rz)) stop = CG_BREAKDOWN;
+    else if (rr <= st->pause_thresh) stop = CG_PAUSED;
+    const T a = st->alpha;
+    const int32_t n_groups = (int32_t)(((int64_t)n + SPMV_BLOCK - 1) / SPMV_BLOCK);
+    const int32_t g0 = xcd_block(), gstep = (int32_t)gridDim.x;
+    if (stop != CG_RUNNING) {
+        for (int32_t g = g0; g < n_groups; g += gstep) {
+            const int32_t i = g * SPMV_BLOCK + (int32_t)threadIdx.x;
+            if (i < n) {
+                const T pi = po[i];
+                x[i] = x[i] + a * pi;
+                pn[i] = pi;
+            }
+        }
+        if (lead) {
+            st->rr = rr;
+            st->iter = k + 1;
+            st->done = stop;
+        }
+        return;
+    }
+    const T beta = rz / st->rz[k & 3];
+    const bool spmv = k + 1 < st->max_iter;   // K1 of iteration k + 1 runs
+    T ppq = T(0);
+    for (int32_t g = g0; g < n_groups; g += gstep) {
+        const int32_t i = g * SPMV_BLOCK + (int32_t)threadIdx.x;
+        if (i >= n) continue;
+        const T pi = po[i];
+        x[i] = x[i] + a * pi;
+        const T pni = dinv[i] * r[i] + beta * pi;
+        pn[i] = pni;
+        if (spmv) {
+            // U entries per trip, every load of a trip issued before its first
+            // product; the products are added in column order as before
+            constexpr int U = 8;
+            T sum = T(0);
+            const int32_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
+            for (int32_t eb = e0; eb < e1; eb += U) {
+                int32_t cj[U];
+                T vv[U], rj[U], dj[U], pj[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const bool in = eb + u < e1;
+                    cj[u] = in ? col[eb + u] : i;
+                    vv[u] = in ? val[eb + u] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    rj[u] = r[cj[u]];
+                    dj[u] = dinv[cj[u]];
+                    pj[u] = po[cj[u]];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (eb + u < e1) sum += vv[u] * (dj[u] * rj[u] + beta * pj[u]);
+            }
+            q[i] = sum;
+            ppq += pni * sum;
+        }
+    }
+    if (spmv) {
+        const T b = block_sum<T, SPMV_BLOCK>(ppq, red);
+        if (threadIdx.x == 0) part[PART_A + xcd_block()] = b;
+    }
+    if (lead) {
+        st->rz[(k + 1) & 3] = rz;
+        st->rr = rr;
+        st->beta = beta;
+        st->iter = k + 1;
+    }
+}
+
 // x64 += (double) x32, then x32 = 0
 __global__ void __launch_bounds__(VEC_BLOCK)
 ir_accumulate(int32_t n, double* __restrict__ x, float* __restrict__ d) {
@@ -664,6 +764,10 @@ struct Cg {
     bool amg = false;
     bool amg_ordered = false;   // the hierarchy of the solve-order copy
     int32_t g_rz = 0;       // partials of (r, z) the finalize and K3 sum
+    // two-launch iteration: the second direction buffer (p_k and p_{k+1}
+    // alternate between p and p_alt; p always names the current one between
+    // calls of iterate)
+    T* p_alt = nullptr;
 };
 
 // the matrix a solve runs on: the fused pattern in the plan's SpMV form, or
@@ -867,6 +971,45 @@ int cg_graph(Cg<T>& c, int chunk, hipGraphExec_t* out) {
     return RP_OK;
 }
 
+// the plan's second direction buffer for the two-launch iteration: the
+// preconditioned-residual vector, which Jacobi solves do not use otherwise
+inline double* alt_direction(rp_plan* p, double*) { return p->d_z; }
+inline float* alt_direction(rp_plan* p, float*) { return p->d_z32; }
+
+// The two-launch form of the chunks below: K1 of the first iteration, then
+// per iteration K2 and the fused K3 + K1 (cg_update_xp_spmv), until the
+// state leaves CG_RUNNING or the budget is spent.  Same kernels' arithmetic,
+// so the same iterates bit for bit.
+template <typename T>
+int iterate_two(Cg<T>& c, int chunk, int32_t max_iter) {
+    RP_TRY(alloc_z(c.plan));
+    if (!c.p_alt) c.p_alt = alt_direction(c.plan, c.p);
+    T* pb[2] = {c.p, c.p_alt};
+    const int32_t k0 = c.h->iter;
+    const dim3 gs(c.g_spmv), bs(SPMV_BLOCK), gv(c.g_vec), bv(VEC_BLOCK);
+#define RP_LAUNCH(NW) \
+    hipLaunchKernelGGL((cg_spmv_pq<T, NW>), gs, bs, 0, c.s, c.n, c.ix, c.val, c.p, c.q, c.part, c.st, c.w)
+    RP_DISPATCH_NW(c.xw_mode, RP_LAUNCH);
+#undef RP_LAUNCH
+    RP_HIP_TRY(hipGetLastError());
+    while (c.h->done == CG_RUNNING && c.h->iter < max_iter) {
+        const int32_t ks = c.h->iter;
+        const int32_t k1 = (int32_t)std::min<int64_t>((int64_t)ks + chunk, max_iter);
+        for (int32_t k = ks; k < k1; ++k) {
+            hipLaunchKernelGGL(cg_update_r<T>, gv, bv, 0, c.s, c.n, k, c.g_spmv, c.r, c.q, c.dinv, c.part, c.st);
+            hipLaunchKernelGGL(cg_update_xp_spmv<T>, gs, bs, 0, c.s, c.n, k, c.g_vec, c.ix.row_ptr, c.ix.col, c.val,
+                               c.r, c.dinv, pb[(k - k0) & 1], pb[(k - k0 + 1) & 1], c.x, c.q, c.part, c.st);
+        }
+        RP_HIP_TRY(hipGetLastError());
+        RP_TRY(read_state(c));
+    }
+    // The current direction: p_{iter} after a completed iteration, or p_k
+    // after a stop in that kernel (it copied p_k forward), or p_k after a
+    // breakdown in K2 of iteration k = iter (the fused kernel did not run).
+    if ((c.h->iter - k0) & 1) std::swap(c.p, c.p_alt);
+    return RP_OK;
+}
+
 // enqueue chunks of up to `chunk` iterations (never past max_iter) until the
 // state leaves CG_RUNNING or the budget is spent.  graph: each chunk is one
 // replay of a captured graph of `chunk` iterations (kernels past max_iter do
@@ -874,7 +1017,9 @@ int cg_graph(Cg<T>& c, int chunk, hipGraphExec_t* out) {
 template <typename T>
 int iterate(Cg<T>& c, int chunk, int32_t max_iter, bool graph, int32_t fused_loop) {
     const bool timed = c.plan->timing.enabled;
-    if (fused_loop == 1 && !timed && !graph && !c.bj_minv && !c.amg) {
+    if (fused_loop == RP_LOOP_AUTO && c.n <= RP_LOOP_TWO_MAX_ROWS && !timed && !graph && !c.bj_minv && !c.amg)
+        return iterate_two(c, chunk, max_iter);
+    if (fused_loop == RP_LOOP_COOPERATIVE && !timed && !graph && !c.bj_minv && !c.amg) {
         // launches of at most LOOP_ITERS iterations keep the barrier counter
         // (3 arrivals per block and iteration) far below 2^32
         constexpr int64_t LOOP_ITERS = 1 << 16;

@@ -187,3 +187,15 @@ def test_plan_create_rejects_overflow_on_host(lib_path):
     out = ctypes.c_void_p()
     rc = rp.rp_plan_create(3, nca, 0, 3, descs, ctypes.byref(out))
     assert rc == rp.RP_ERR_OVERFLOW and out.value is None
+
+
+def test_binding_constants_match_the_header(lib_path):
+    """Every numeric RP_* constant the binding defines has the header's value."""
+    import paper_2510_08536_amd.rp as rp
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    defs = dict(re.findall(r"^#define\s+(RP_\w+)\s+(-?[0-9][0-9.eE+-]*)\s*$", text, flags=re.M))
+    assert "RP_LOOP_TWO_MAX_ROWS" in defs and "RP_PRECOND_AMG" in defs
+    shared = [k for k in defs if hasattr(rp, k)]
+    assert len(shared) >= 20, shared
+    wrong = {k: (defs[k], getattr(rp, k)) for k in shared if float(defs[k]) != float(getattr(rp, k))}
+    assert not wrong, wrong

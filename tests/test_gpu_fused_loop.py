@@ -1,5 +1,6 @@
-"""CG iterations in one cooperative launch (rp_solve_opts.fused_loop = 1)
-against the oracle and against the three-kernel iteration (fused_loop = 0).
+"""CG iterations in one cooperative launch (rp_solve_opts.fused_loop =
+RP_LOOP_COOPERATIVE) against the oracle and against the three-kernel
+iteration (RP_LOOP_THREE).
 
 The single-launch loop does the arithmetic of the three-kernel iteration with
 per-block partial sums over a different grid, so its iterates differ from the
@@ -51,7 +52,7 @@ def test_loop_solve_matches_oracle(name, precision):
     x_or, st, it_or, rs_or, _ = oracle.pcg(m, val64, b, tol=1e-8)
     assert st == 0 and rs_or == 0
     res = {}
-    for fl in (1, 0):
+    for fl in (1, 2):
         x, info = plan.solve(dev_tensor(b), tol=1e-8, precision=precision, fused_loop=fl)
         xh = x.cpu().numpy()
         rr = oracle.true_relres(m, val64, b, xh)
