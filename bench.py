@@ -452,8 +452,10 @@ def main():
                                          "built once: amg_hierarchy.setup_ms; a value update refreshes the "
                                          "coarse values: refresh_ms)"),
         "cg_loop": dict(loop, note="last timestep's system, x0 = 0, tol 1e-8, 3 solves each (median); "
-                                   "single_launch: the iterations in one cooperative launch with grid-wide "
-                                   "barriers, three_kernel: one launch per phase") if loop else None,
+                                   "three_kernel: one launch per phase; two_launch: the x and p update "
+                                   "fused with the next SpMV (systems of at most 2^18 rows); single_launch: "
+                                   "the iterations in one cooperative launch with grid-wide barriers")
+        if loop else None,
         "fp64_warm_start": ({"ms_per_solve": round(float(np.median([wm for wm, _ in warm])), 3),
                              "iters": int(np.median([wi for _, wi in warm])),
                              "note": "x0 = previous timestep's x; values differ by up to 5 % between timesteps"}

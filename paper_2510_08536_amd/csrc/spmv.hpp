@@ -297,7 +297,6 @@ __device__ __forceinline__ GroupRow<T> spmv_group_coded(const SpmvIdx& ix, const
     for (int j = 0; j < GOI_KMAX; ++j) off[j] = offp[j];
     const int32_t al = base & ~(E - 1);            // packs start on a multiple of E
     const int32_t npk = (end - al + E - 1) / E;
-    const int32_t last = npk > 0 ? npk - 1 : 0;
     // FP64: the block's diagonal window x[r0 - XN, r0 + SPMV_BLOCK + XN) goes
     // to LDS, and taps with |offset| <= XN read it there instead of memory.
     // (FP32 runs slower with it and takes every tap from memory.)
@@ -321,17 +320,18 @@ __device__ __forceinline__ GroupRow<T> spmv_group_coded(const SpmvIdx& ix, const
     if ((t & 63) == 63) wtot[t >> 6] = inc;
     // values: whole 16-byte packs straight from HBM into LDS.  The load
     // writes lane-linearly from a wave-uniform base, and pack k of the stretch
-    // lands in LDS slot k.  Lanes past the stretch re-read its last pack into
-    // their own (unused) slot; that pack may reach E - 1 elements past `end`
-    // (SPMV_PAD).
+    // lands in LDS slot k.  Only lanes inside the stretch load (a wave wholly
+    // past it issues nothing); the last pack may reach E - 1 elements past
+    // `end` (SPMV_PAD).
     constexpr int U = SPMV_CAP / E / SPMV_BLOCK;
     typedef __attribute__((address_space(3))) void* LdsPtr;
     const int32_t wave0 = t & ~63;
 #pragma unroll
     for (int u = 0; u < U; ++u)
-        __builtin_amdgcn_global_load_lds((void*)(reinterpret_cast<const VP*>(val + al) + min(t + u * SPMV_BLOCK, last)),
-                                         (LdsPtr)(reinterpret_cast<VP*>(lds) + u * SPMV_BLOCK + wave0), 16, 0,
-                                         SPMV_NT_AUX);
+        if (t + u * SPMV_BLOCK < npk)
+            __builtin_amdgcn_global_load_lds((void*)(reinterpret_cast<const VP*>(val + al) + (t + u * SPMV_BLOCK)),
+                                             (LdsPtr)(reinterpret_cast<VP*>(lds) + u * SPMV_BLOCK + wave0), 16, 0,
+                                             SPMV_NT_AUX);
     // x of the present entries of the first KH taps, all issued before the
     // first use; taps KH.. (groups with more offsets) follow after the sums.
     // FP64 takes 8 at a time: the registers of all 16 would cost it a wave

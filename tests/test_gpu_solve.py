@@ -121,19 +121,35 @@ def test_windows_do_not_change_solves():
     plan.close()
 
 
-@pytest.mark.parametrize("name", ["c1", "rcb_mixed", "ragged_rcb7"])
+FORM_CASES = {
+    # 27-point stencil: more offsets than a coded group holds (CSR groups only)
+    "box27": lambda: synth.small((10, 9, 8), ("blocks", 2, 1, 1), kappa=(1e-2, 1.0), seed=25, stencil=27),
+    # rank rows of 64 cells: offsets +-1, +-64, +-384 in every coded group
+    "rows64": lambda: synth.small((64, 6, 8), ("blocks", 1, 1, 2), kappa=(1e-3, 1.0), seed=26),
+}
+
+
+@pytest.mark.parametrize("name", ["c1", "rcb_mixed", "ragged_rcb7", "chain", "stretched", "box27", "rows64"])
 def test_spmv_form_does_not_change_solves(name):
     """The offset-coded and the CSR index form give the same products and row
-    sums, so FP64 and mixed solves are bit-identical in either form (and with
-    the x windows of the CSR groups on)."""
-    w, m, val64, plan = _setup(name)
+    sums, so FP64 and both mixed solves are bit-identical in either form (and
+    with the x windows of the CSR groups on), with three and with two launches
+    per iteration."""
+    from paper_2510_08536_amd import RP_LOOP_THREE
+    if name in FORM_CASES:
+        w = FORM_CASES[name]()
+        plan = make_plan(w)
+        update(plan, share_values(w))
+    else:
+        w, m, val64, plan = _setup(name)
     b = dev_tensor(w.rhs())
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed", "mixed_rr"):
         runs = []
-        for coded, windows in ((True, False), (False, False), (False, True), (True, True)):
+        for coded, windows, fl in ((True, False, 0), (False, False, 0), (False, True, 0), (True, True, 0),
+                                   (True, False, RP_LOOP_THREE), (False, False, RP_LOOP_THREE)):
             plan.set_spmv_format(coded)
             plan.set_spmv_windows(windows)
-            x, info = plan.solve(b, precision=prec)
+            x, info = plan.solve(b, precision=prec, fused_loop=fl)
             runs.append((x, info["iters"], info["outer_iters"]))
         for x, it, outer in runs[1:]:
             assert (it, outer) == runs[0][1:] and torch_mod().equal(x, runs[0][0]), (name, prec)
