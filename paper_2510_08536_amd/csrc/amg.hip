@@ -24,6 +24,8 @@
 // Every product and sum is one rounding in the order the definition states
 // (row sums in column order, aggregate sums over the members ascending), so
 // the hierarchy and one V-cycle are bit-exact against the serial definition.
+// The levels from the first one with at most AMG_TAIL_ROWS rows down run in
+// one workgroup (amg_tail), with the same operations in the same order.
 //
 // Setup runs on the device: matching rounds (the host reads one counter per
 // round), scans for the numbering, per-coarse-row key lists (aggregate of the
@@ -526,6 +528,112 @@ amg_coarse(int32_t n, const T* __restrict__ cinv, const T* __restrict__ r, T* __
     }
 }
 
+// ---------------------------------------------------------------------------
+// The tail of the V-cycle: every level from the first one with at most
+// AMG_TAIL_ROWS rows down to the coarsest, in one workgroup.  Each step is
+// the corresponding kernel's above, row by row with the same operations in
+// the same order (rows' products summed in column order from 0, members in
+// ascending order, the coarsest inverse times r with j ascending), and the
+// workgroup barrier stands where the level kernels had a launch boundary.
+// On the small levels a launch costs more than its work.
+// ---------------------------------------------------------------------------
+constexpr int64_t AMG_TAIL_ROWS = 1024;
+constexpr int TB = 1024;   // threads of the tail workgroup
+
+template <typename T>
+struct TailLevel {
+    int32_t n;
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const T* val;
+    const T* dinv;
+    const int32_t* agg;       // all tail levels but the coarsest
+    const int32_t* mem_ptr;
+    const int32_t* mem;
+    T* v[4];                  // in, x, t, out (x and t on smoothed levels)
+};
+
+// row i of A x: U entries per trip, every load of a trip issued before its
+// first product; the products are added in column order from 0
+template <typename T>
+__device__ __forceinline__ T tail_row_sum(const TailLevel<T>& L, const T* __restrict__ x, int32_t i) {
+#pragma clang fp contract(off)
+    constexpr int U = 8;
+    T s = T(0);
+    const int32_t e0 = L.row_ptr[i], e1 = L.row_ptr[i + 1];
+    for (int32_t eb = e0; eb < e1; eb += U) {
+        int32_t c[U];
+        T v[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool in = eb + u < e1;
+            c[u] = in ? L.col[eb + u] : 0;
+            v[u] = in ? L.val[eb + u] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (eb + u < e1) s += v[u] * xv[u];
+    }
+    return s;
+}
+
+// y = V_lt(r) on levels lt .. last (lv[0] is level lt; r in lv[0].v[0], y
+// to lv[0].v[3])
+template <typename T>
+__global__ void __launch_bounds__(TB)
+amg_tail(int32_t lt, int32_t last, const TailLevel<T>* __restrict__ lv, const T* __restrict__ cinv, T omega,
+         const int32_t* gate) {
+#pragma clang fp contract(off)
+    if (gate && *gate < 0) return;
+    const int32_t t = threadIdx.x;
+    for (int32_t l = lt; l < last; ++l) {
+        const TailLevel<T>& L = lv[l - lt];
+        const TailLevel<T>& C = lv[l - lt + 1];
+        const T* r = L.v[0];
+        const T* src = r;   // what restricts to the coarse level
+        if (l % 2 == 0) {
+            for (int32_t i = t; i < L.n; i += TB) L.v[1][i] = omega * (L.dinv[i] * r[i]);
+            __syncthreads();
+            for (int32_t i = t; i < L.n; i += TB) L.v[2][i] = r[i] - tail_row_sum(L, L.v[1], i);
+            __syncthreads();
+            src = L.v[2];
+        }
+        for (int32_t I = t; I < C.n; I += TB) {
+            T s = T(0);
+            for (int32_t m = L.mem_ptr[I]; m < L.mem_ptr[I + 1]; ++m) s += src[L.mem[m]];
+            C.v[0][I] = s;
+        }
+        __syncthreads();
+    }
+    {
+        const TailLevel<T>& L = lv[last - lt];
+        const int32_t n = L.n;
+        for (int32_t i = t; i < n; i += TB) {
+            T s = T(0);
+            for (int32_t j = 0; j < n; ++j) s += cinv[(int64_t)i * n + j] * L.v[0][j];
+            L.v[3][i] = s;
+        }
+        __syncthreads();
+    }
+    for (int32_t l = last - 1; l >= lt; --l) {
+        const TailLevel<T>& L = lv[l - lt];
+        const T* e = lv[l - lt + 1].v[3];
+        if (l % 2 == 1) {
+            for (int32_t i = t; i < L.n; i += TB) L.v[3][i] = e[L.agg[i]];
+        } else {
+            T* x = L.v[1];
+            for (int32_t i = t; i < L.n; i += TB) x[i] = x[i] + e[L.agg[i]];
+            __syncthreads();
+            const T* r = L.v[0];
+            for (int32_t i = t; i < L.n; i += TB)
+                L.v[3][i] = x[i] + omega * (L.dinv[i] * (r[i] - tail_row_sum(L, x, i)));
+        }
+        __syncthreads();
+    }
+}
+
 // the level-0 system of a hierarchy: the fused pattern (with its
 // offset-coded SpMV form) or the solve-order copy (plain CSR)
 struct Src {
@@ -556,6 +664,7 @@ struct Prec<double> {
     static const double* dinv(const AmgLevel& L) { return L.dinv64; }
     static double** vec(AmgLevel& L) { return L.vec64; }
     static const double* cinv(const AmgHier& h) { return h.cinv64; }
+    static void*& tail(AmgHier& h) { return h.tail64; }
     static const double* val0(const Src& q) { return q.val64; }
     static const double* dinv0(const Src& q) { return q.dinv64; }
 };
@@ -565,6 +674,7 @@ struct Prec<float> {
     static const float* dinv(const AmgLevel& L) { return L.dinv32; }
     static float** vec(AmgLevel& L) { return L.vec32; }
     static const float* cinv(const AmgHier& h) { return h.cinv32; }
+    static void*& tail(AmgHier& h) { return h.tail32; }
     static const float* val0(const Src& q) { return q.val32; }
     static const float* dinv0(const Src& q) { return q.dinv32; }
 };
@@ -585,6 +695,25 @@ int alloc_vectors(AmgHier& h) {
             if (need && !v[k]) RP_HIP_TRY(hipMalloc(&v[k], bytes));
         }
     }
+    // the tail's per-level pointers, once the vectors exist
+    void*& tab = Prec<T>::tail(h);
+    if (h.tail_level > 0 && !tab) {
+        std::vector<TailLevel<T>> tl;
+        for (int32_t l = h.tail_level; l < h.n_levels; ++l) {
+            AmgLevel& L = h.lev[l];
+            T** v = Prec<T>::vec(L);
+            tl.push_back(TailLevel<T>{(int32_t)L.n, L.row_ptr, L.col, Prec<T>::val(L), Prec<T>::dinv(L), L.agg,
+                                      L.mem_ptr, L.mem, {v[0], v[1], v[2], v[3]}});
+        }
+        void* d = nullptr;
+        RP_HIP_TRY(hipMalloc(&d, sizeof(TailLevel<T>) * tl.size()));
+        const hipError_t e = hipMemcpy(d, tl.data(), sizeof(TailLevel<T>) * tl.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            RP_HIP_TRY(e);
+        }
+        tab = d;
+    }
     return RP_OK;
 }
 
@@ -601,6 +730,12 @@ int vcycle(AmgHier& h, const Src& q, int32_t l, const T* r, T* y, T* part, int32
     const int32_t n = (int32_t)L.n;
     const T omega = (T)RP_AMG_OMEGA;
     const bool want = part != nullptr;
+    if (l > 0 && l == h.tail_level) {
+        hipLaunchKernelGGL(amg_tail<T>, dim3(1), dim3(TB), 0, s, l, h.n_levels - 1,
+                           (const TailLevel<T>*)Prec<T>::tail(h), Prec<T>::cinv(h), omega, gate);
+        RP_HIP_TRY(hipGetLastError());
+        return RP_OK;
+    }
     if (l == h.n_levels - 1) {
 #define RP_LAUNCH(PT, RRF)                                                                                       \
     hipLaunchKernelGGL((amg_coarse<T, PT, RRF>), dim3(1), dim3(AB), 0, s, n, Prec<T>::cinv(h), r, y, part, n_part, \
@@ -818,7 +953,7 @@ void free_hier(AmgHier*& hp) {
     AmgHier& h = *hp;
     // every level: a failed coarsening leaves arrays on the level it was building
     for (int32_t l = 0; l < AMG_MAX_LEVELS; ++l) free_level(h.lev[l]);
-    for (void* a : {(void*)h.cinv64, (void*)h.cinv32, (void*)h.cwork, (void*)h.flag})
+    for (void* a : {(void*)h.cinv64, (void*)h.cinv32, (void*)h.cwork, (void*)h.flag, h.tail64, h.tail32})
         if (a) (void)hipFree(a);
     delete hp;
     hp = nullptr;
@@ -870,6 +1005,9 @@ int amg_setup(rp_plan* p, hipStream_t s, bool ordered) {
         if (e != hipSuccess)
             return fail((set_error("launching amg_gvals failed: %s", hipGetErrorString(e)), RP_ERR_HIP));
     }
+    // the first level below level 0 small enough for the one-workgroup tail
+    for (int32_t l = 1; l < h.n_levels && h.tail_level == 0; ++l)
+        if (h.lev[l].n <= AMG_TAIL_ROWS) h.tail_level = l;
     const int64_t nL = h.lev[h.n_levels - 1].n;
     h.cinv64 = dalloc<double>(nL * nL);
     h.cinv32 = dalloc<float>(nL * nL);

@@ -149,6 +149,11 @@ struct AmgHier {
     double* cwork = nullptr;      // [n_L^2] elimination work
     uint32_t* flag = nullptr;     // [2] pair counter / error bits
     int64_t version = -1;         // values_version the coarse values belong to
+    // the V-cycle below tail_level runs in one workgroup (amg.hip); its
+    // per-level pointers per precision, on the device
+    int32_t tail_level = 0;       // 0: none
+    void* tail64 = nullptr;
+    void* tail32 = nullptr;
 };
 
 // ---------------------------------------------------------------------------
