@@ -80,6 +80,8 @@ extern "C" {
                                      rp_plan_amg_setup) */
 #define RP_AMG_OMEGA 0.8          /* damping of the multigrid's Jacobi sweeps */
 #define RP_AMG_COARSE_MAX 64      /* rows of the coarsest level at most (dense inverse) */
+#define RP_AMG_TAIL_ROWS 1024     /* the V-cycle from the first level (below the fine one)
+                                     with at most this many rows down runs in one workgroup */
 
 /* ---- launches per Jacobi-PCG iteration (rp_solve_opts.fused_loop) ------- */
 #define RP_LOOP_AUTO 0            /* two launches on systems of at most RP_LOOP_TWO_MAX_ROWS

@@ -537,7 +537,7 @@ amg_coarse(int32_t n, const T* __restrict__ cinv, const T* __restrict__ r, T* __
 // workgroup barrier stands where the level kernels had a launch boundary.
 // On the small levels a launch costs more than its work.
 // ---------------------------------------------------------------------------
-constexpr int64_t AMG_TAIL_ROWS = 1024;
+constexpr int64_t AMG_TAIL_ROWS = RP_AMG_TAIL_ROWS;
 constexpr int TB = 1024;   // threads of the tail workgroup
 
 template <typename T>

@@ -55,6 +55,7 @@ RP_PRECOND_JACOBI, RP_PRECOND_BLOCK_JACOBI, RP_PRECOND_AMG = 0, 1, 2
 RP_BJ_MAX_BLOCK = 8
 RP_AMG_OMEGA = 0.8
 RP_AMG_COARSE_MAX = 64
+RP_AMG_TAIL_ROWS = 1024
 RP_LOOP_AUTO, RP_LOOP_COOPERATIVE, RP_LOOP_THREE = 0, 1, 2
 RP_LOOP_TWO_MAX_ROWS = 262144
 RP_NOALLOC_MAX_RANKS = 4096

@@ -59,13 +59,25 @@ def _compare_hierarchy(plan, h, what):
     assert_bits_equal(plan.amg_coarse_inverse(), h.coarse_inverse(), f"{what} coarsest inverse")
 
 
+# first level of the one-workgroup tail of the V-cycle (levels below the
+# fine one with at most RP_AMG_TAIL_ROWS rows) for the cases above: the tail
+# is the coarsest level alone, several levels from level 1, or deeper levels
+TAIL_FROM = {"tiny": 1, "single": None, "chain": 1, "box27": 1, "ragged_rcb7": 2, "c1": 5}
+
+
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_hierarchy_and_vcycle_bit_exact(name):
+    from paper_2510_08536_amd.rp import RP_AMG_TAIL_ROWS
     w = CASES[name]()
     m, v64, plan = _setup(w)
     h = oracle.AmgHierarchy(m, v64)
     plan.amg_setup()
     _compare_hierarchy(plan, h, name)
+    sizes = [h.level_size(l) for l in range(h.n_levels)]
+    tail = next((l for l in range(1, len(sizes)) if sizes[l] <= RP_AMG_TAIL_ROWS), None)
+    print(f"{name}: levels {sizes}, one-workgroup tail from level {tail}")
+    if name in TAIL_FROM:
+        assert tail == TAIL_FROM[name], (name, sizes, tail)
     rng = np.random.default_rng(5)
     for _ in range(2):
         r = rng.uniform(-1, 1, m.n_rows)
