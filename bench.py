@@ -41,6 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+TIMING_STRIDE = 8                # kernel timing records every 8th launch (rp_plan_set_timing)
 METRIC = "ms per pressure solve to rel.res 1e-8 + SpMV HBM GB/s, FP64 vs mixed, 1 GPU"
 
 
@@ -250,7 +251,10 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] warmup done ({a.warmup} steps)", flush=True)
 
-    plan.set_timing(True)
+    # HIP events around every TIMING_STRIDE-th launch of the timed kernels: an
+    # event pair costs the stream several microseconds, so timing every launch
+    # would slow the timed solves it measures
+    plan.set_timing(TIMING_STRIDE)
     recs = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -489,7 +493,8 @@ def main():
                      "frac": round(spmv_gbs / HBM_PEAK_GBS, 4),
                      "bytes_per_launch": spmv64_bytes, "bytes_basis": "12 nnz + 20 n + 4 (FP64 CSR SpMV)",
                      "kernel_bytes_per_launch": kern64_bytes, "avg_launch_ms": round(spmv_avg_ms, 5),
-                     "launches": n_spmv, "traffic": None if rcm else profiled_traffic(a.config),
+                     "launches": n_spmv, "timed_launches": f"HIP events around every {TIMING_STRIDE}th launch "
+                                                           "of the timed steps", "traffic": None if rcm else profiled_traffic(a.config),
                      "traffic_note": "HBM bytes/launch from FETCH_SIZE+WRITE_SIZE (profiles/traffic_c3.md), "
                                      "scaled by a 2 GiB copy; null if the kernel changed since"},
     }

@@ -482,9 +482,12 @@ int rp_sync(rp_plan* plan);
 const char* rp_last_error(void);
 
 /* Kernel timing with HIP events on the launch stream (off by default).  While
- * enabled, every launch of kernel `kernel` (RP_KERNEL_*) is bracketed by an
- * event pair; rp_plan_kernel_stats returns the launch count and the summed
- * device time since enabling. */
+ * enabled, every enable-th launch of kernel `kernel` (RP_KERNEL_*) is
+ * bracketed by an event pair (enable = 1: every launch; an event pair costs
+ * the stream several microseconds, so a stride above 1 keeps the timed run
+ * close to an untimed one); rp_plan_kernel_stats returns the count of the
+ * recorded launches that did work and their summed device time since
+ * enabling.  enable = 0 switches timing off; below 0 is an argument error. */
 #define RP_KERNEL_SPMV64 0        /* FP64 CSR SpMV inside CG (q = A p with p.q) */
 #define RP_KERNEL_SPMV32 1        /* FP32 CSR SpMV inside the inner CG */
 #define RP_KERNEL_SCATTER 2       /* value update (reorder by P) */

@@ -30,13 +30,18 @@ void clear_error() { g_err[0] = 0; }
 int timing_begin(rp_plan* p, int kernel, hipStream_t s) {
     if (!p->timing.enabled) return RP_OK;
     EventPool& e = p->timing.pool[kernel];
+    const int64_t k = e.seen++;
+    e.open = k % p->timing.stride == 0;
+    if (!e.open) return RP_OK;
     if (e.used == (int64_t)e.start.size()) {
         hipEvent_t a, b;
         RP_HIP_TRY(hipEventCreate(&a));
         RP_HIP_TRY(hipEventCreate(&b));
         e.start.push_back(a);
         e.stop.push_back(b);
+        e.idx.push_back(0);
     }
+    e.idx[e.used] = k - e.chunk0;
     RP_HIP_TRY(hipEventRecord(e.start[e.used], s));
     return RP_OK;
 }
@@ -44,19 +49,24 @@ int timing_begin(rp_plan* p, int kernel, hipStream_t s) {
 int timing_end(rp_plan* p, int kernel, hipStream_t s) {
     if (!p->timing.enabled) return RP_OK;
     EventPool& e = p->timing.pool[kernel];
+    if (!e.open) return RP_OK;
     RP_HIP_TRY(hipEventRecord(e.stop[e.used], s));
     ++e.used;
+    e.open = false;
     return RP_OK;
 }
 
+// adds the recorded launches among the first `keep` launches since the last
+// collection (the rest found the solve stopped) to the kernel's totals
 int timing_collect(rp_plan* p, int kernel, int64_t keep) {
     EventPool& e = p->timing.pool[kernel];
     if (!p->timing.enabled || e.used == 0) {
         e.used = 0;
+        e.chunk0 = e.seen;
         return RP_OK;
     }
-    keep = std::min<int64_t>(std::max<int64_t>(keep, 0), e.used);
-    for (int64_t i = 0; i < keep; ++i) {
+    for (int64_t i = 0; i < e.used; ++i) {
+        if (e.idx[i] >= keep) continue;
         float ms = 0.f;
         RP_HIP_TRY(hipEventSynchronize(e.stop[i]));
         RP_HIP_TRY(hipEventElapsedTime(&ms, e.start[i], e.stop[i]));
@@ -64,6 +74,7 @@ int timing_collect(rp_plan* p, int kernel, int64_t keep) {
         p->timing.total_ms[kernel] += ms;
     }
     e.used = 0;
+    e.chunk0 = e.seen;
     return RP_OK;
 }
 
@@ -674,11 +685,17 @@ int rp_plan_set_timing(rp_plan* p, int32_t enable) {
     RP_CHECK(p != nullptr, RP_ERR_ARG, "plan is NULL");
     RP_TRY(activate(p));
     RP_HIP_TRY(hipDeviceSynchronize());
+    RP_CHECK(enable >= 0, RP_ERR_ARG, "enable must be 0 (off) or the stride of the recorded launches (>= 1)");
     p->timing.enabled = enable != 0;
+    p->timing.stride = enable > 0 ? enable : 1;
     for (int k = 0; k < RP_N_KERNELS; ++k) {
         p->timing.launches[k] = 0;
         p->timing.total_ms[k] = 0.0;
-        p->timing.pool[k].used = 0;
+        EventPool& e = p->timing.pool[k];
+        e.used = 0;
+        e.seen = 0;
+        e.chunk0 = 0;
+        e.open = false;
     }
     return RP_OK;
 }

@@ -161,11 +161,16 @@ struct AmgHier {
 // ---------------------------------------------------------------------------
 struct EventPool {
     std::vector<hipEvent_t> start, stop;
+    std::vector<int64_t> idx;   // launch of each recorded pair, counted from the chunk's first
     int64_t used = 0;
+    int64_t seen = 0;           // launches since timing was enabled
+    int64_t chunk0 = 0;         // `seen` at the last collection
+    bool open = false;          // the current launch is being recorded
 };
 
 struct Timing {
     bool enabled = false;
+    int32_t stride = 1;         // every stride-th launch of a kernel is recorded
     int64_t launches[RP_N_KERNELS] = {0, 0, 0};
     double total_ms[RP_N_KERNELS] = {0, 0, 0};
     EventPool pool[RP_N_KERNELS];

@@ -522,8 +522,12 @@ class Plan:
         return g
 
     # -- timing ---------------------------------------------------------------
-    def set_timing(self, enable: bool):
-        _check(rp_plan_set_timing(self._h, int(bool(enable))), "rp_plan_set_timing")
+    def set_timing(self, enable):
+        """False / 0: off; True / 1: HIP events around every launch of the
+        timed kernels; n > 1: around every n-th launch."""
+        if isinstance(enable, bool):
+            enable = int(enable)
+        _check(rp_plan_set_timing(self._h, int(enable)), "rp_plan_set_timing")
 
     def kernel_stats(self, kernel: int):
         n, ms = C.c_int64(), C.c_double()

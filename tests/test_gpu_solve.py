@@ -275,6 +275,31 @@ def test_kernel_timing_counts_iterations():
     plan.close()
 
 
+@pytest.mark.parametrize("stride", [3, 8])
+@pytest.mark.parametrize("check_every", [5, 32])
+def test_kernel_timing_stride(stride, check_every):
+    """Timing every stride-th launch: the launches 0, stride, 2 stride, ...
+    of the solve that did work are recorded (those past the stop inside the
+    last host chunk are not), and their mean matches timing every launch."""
+    from paper_2510_08536_amd import RP_KERNEL_SPMV64, RpError
+    w, m, val64, plan = _setup("c1")
+    b = dev_tensor(w.rhs())
+    plan.set_timing(1)
+    x1, info1 = plan.solve(b, tol=1e-8, check_every=check_every)
+    n1, ms1 = plan.kernel_stats(RP_KERNEL_SPMV64)
+    assert n1 == info1["iters"]
+    plan.set_timing(stride)
+    x, info = plan.solve(b, tol=1e-8, check_every=check_every)
+    n, ms = plan.kernel_stats(RP_KERNEL_SPMV64)
+    assert info["iters"] == info1["iters"] and torch_mod().equal(x, x1)
+    assert n == -(-info["iters"] // stride) and ms > 0, (n, info["iters"], stride)
+    assert 0.5 < (ms / n) / (ms1 / n1) < 2.0
+    plan.set_timing(False)
+    with pytest.raises(RpError):
+        plan.set_timing(-1)
+    plan.close()
+
+
 def test_update_and_solve_on_a_side_stream():
     """The library enqueues on the stream it is given (torch's current one by
     default): the same update and solve on a second stream give the same
